@@ -1,0 +1,171 @@
+/*
+ * gmm.h - C ABI of the RGB-D mixture-of-Gaussians background segmentation library (gfx950).
+ *
+ * The library runs, per pixel and per frame, the adaptive Gaussian-mixture background model
+ * of Sec. III.A of "GPU based GMM segmentation of Kinect data" (Amamra, Mouats, Aouf): M
+ * Gaussians per pixel with means, variances and positive weights summing to one; a match test
+ * against the components in decreasing w/sigma order; an online update of weights, means and
+ * variances (with replacement of the least probable component on no match); selection of the
+ * background components by the cumulative-weight threshold T; and classification of the pixel
+ * as foreground when it fits no background component. Update rules the paper leaves to its
+ * reference [6] (Stauffer and Grimson) follow that method. The colour image (uint8 RGB) and the
+ * depth map (uint16 millimetres) are modelled separately (Sec. III.B) and their two binary
+ * foreground images are fused by the counter rule of List 1 (Sec. III.C).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a gmm_status. Arguments are validated synchronously, before any
+ *     device work; on error nothing is enqueued and gmm_last_error() describes the problem.
+ *     The library never aborts and never throws across this boundary.
+ *   - Frame and mask pointers are DEVICE pointers owned by the caller. They must stay valid
+ *     until the stream has executed the enqueued work.
+ *   - `stream` is a hipStream_t (NULL = the device's null stream). Apply and fuse calls are
+ *     asynchronous with respect to the host.
+ *   - Foreground masks are bit-packed: ceil(width*height/64) uint64 words; word i holds pixels
+ *     64i .. 64i+63 of the row-major frame, least significant bit first; pad bits are 0.
+ *     Mask pointers must be 8-byte aligned.
+ *   - A handle is not thread-safe; distinct handles are independent. Work on one handle must be
+ *     ordered by the caller (one stream, or events), since every call reads and rewrites the
+ *     handle's per-pixel state.
+ *   - Execution faults surface at the caller's synchronisation; the handle's state is then
+ *     unspecified.
+ */
+#ifndef RGBD_GMM_H
+#define RGBD_GMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GMM_OK = 0,
+  GMM_ERR_INVALID_ARG = -1,    /* argument outside its documented range or layout         */
+  GMM_ERR_OUT_OF_MEMORY = -2,  /* a device or host allocation failed                      */
+  GMM_ERR_DEVICE = -3,         /* a HIP runtime call or kernel launch failed              */
+  GMM_ERR_STATE = -4,          /* the call does not apply to this handle (e.g. fuse on a
+                                  single-modality handle)                                  */
+  GMM_ERR_UNSUPPORTED = -5     /* a (M, state dtype) combination that is not compiled      */
+} gmm_status;
+
+/* modality bit mask */
+enum { GMM_RGB = 1, GMM_DEPTH = 2 };
+/* storage type of the per-pixel mixture state (arithmetic is always fp32) */
+enum { GMM_F32 = 0, GMM_F16 = 1, GMM_BF16 = 2 };
+/* depth value 0 ("no reading" on a Kinect-class sensor) */
+enum { GMM_HOLE_SKIP = 0,      /* state untouched, pixel classified background             */
+       GMM_HOLE_AS_VALUE = 1 };/* 0 is treated as an ordinary distance                     */
+
+/*
+ * Model parameters (Sec. III.A): M Gaussians per pixel (the paper uses 3 <= M <= 5; 1 and 2
+ * are accepted for closed-form tests), learning rate alpha (also the rate of the mean and
+ * variance updates), match threshold k in standard deviations (strict: d^2 < k^2 sigma^2),
+ * background weight threshold T. Index 0 of the two-element arrays is colour, 1 is depth.
+ */
+typedef struct {
+  int32_t width, height;   /* > 0, width*height < 2^31                                    */
+  int32_t modalities;      /* GMM_RGB, GMM_DEPTH or both                                    */
+  int32_t M;               /* 1..5                                                          */
+  float alpha;             /* (0, 1]                                                        */
+  float k;                 /* > 0                                                           */
+  float T;                 /* (0, 1)                                                        */
+  float sigma0[2];         /* > 0: standard deviation of a newly created component          */
+  float var_min[2];        /* 0 < var_min <= sigma0^2: floor of every variance              */
+  float w_init;            /* (0, 1]: weight given to a new component before renormalising  */
+  int32_t hole_policy;     /* GMM_HOLE_SKIP or GMM_HOLE_AS_VALUE                            */
+  int32_t state_dtype;     /* GMM_F32, GMM_F16 or GMM_BF16                                  */
+  int32_t device;          /* HIP device ordinal                                            */
+} gmm_config;
+
+typedef struct gmm_handle gmm_handle;
+
+/*
+ * Fill `cfg` with this library's defaults for a width x height stream: alpha = 0.01, k = 2.5,
+ * T = 0.7, sigma0 = {30, 50}, var_min = {(0.1 sigma0)^2} = {9, 25}, w_init = alpha,
+ * GMM_HOLE_SKIP, GMM_F32, device 0. The caller may then change any field.
+ */
+gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, int32_t modalities,
+                              int32_t M);
+
+/*
+ * Create a handle: validates `cfg`, allocates the per-pixel state on cfg->device and
+ * initialises it synchronously - every component empty (w = 0, mu = 0, var = sigma0^2), and
+ * for two-modality handles the fusion state of List 1 at I = 0, cpt = 0.
+ * The handle owns all of its device memory. *out is set only on success.
+ */
+gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out);
+
+/* Release a handle (synchronises the last stream it used first). NULL is a no-op. */
+gmm_status gmm_destroy(gmm_handle* h);
+
+/*
+ * Advance the model one frame and classify it (Sec. III.A, per modality; Sec. III.B keeps the
+ * two modalities separate).
+ *   rgb        device HWC interleaved uint8 R,G,B; row y starts at rgb + y*rgb_pitch_bytes
+ *              (pitch >= 3*width). NULL exactly when the handle has no colour modality.
+ *   depth      device uint16 millimetres, row pitch depth_pitch_bytes (even, >= 2*width);
+ *              NULL exactly when the handle has no depth modality.
+ *   fg_rgb     device output mask of the colour model (see the mask layout above);
+ *   fg_depth   device output mask of the depth model. Each is required for its modality and
+ *              must be NULL for an absent one.
+ * The fusion state of the handle is not touched (see gmm_fuse / gmm_apply_frame_fused).
+ */
+gmm_status gmm_apply_frame(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_bytes,
+                           const uint16_t* depth, int64_t depth_pitch_bytes, uint64_t* fg_rgb,
+                           uint64_t* fg_depth, void* stream);
+
+/*
+ * Fuse a colour and a depth foreground mask by List 1 (Sec. III.C), per pixel, updating the
+ * handle's persistent fused bit I and counter cpt, and write the new I as the fused mask.
+ * The depth foreground is taken as already registered to the colour frame (same size).
+ * Requires a handle with both modalities, else GMM_ERR_STATE.
+ */
+gmm_status gmm_fuse(gmm_handle* h, const uint64_t* fg_rgb, const uint64_t* fg_depth,
+                    uint64_t* fused, void* stream);
+
+/*
+ * The whole per-frame path in one launch: both mixture updates and List 1 fusion. Same
+ * arguments as gmm_apply_frame plus the fused output mask. Bit-identical (masks and state) to
+ * gmm_apply_frame followed by gmm_fuse. Requires both modalities, else GMM_ERR_STATE.
+ */
+gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_bytes,
+                                 const uint16_t* depth, int64_t depth_pitch_bytes,
+                                 uint64_t* fg_rgb, uint64_t* fg_depth, uint64_t* fused,
+                                 void* stream);
+
+/* Text of the last error on the calling thread; valid until that thread's next call. */
+const char* gmm_last_error(void);
+
+/* Device bytes held by the handle's per-pixel state. */
+gmm_status gmm_state_bytes(const gmm_handle* h, size_t* device_bytes);
+
+/*
+ * Number of doubles in the canonical state layout used by gmm_read_state / gmm_write_state:
+ *   [colour block][depth block][I][cpt]
+ * colour block: 5 x M x npix  parameters (muR, muG, muB, var, w), each rank-major;
+ * depth block:  3 x M x npix  parameters (mu, var, w);
+ * I and cpt:    npix each, present only for two-modality handles.
+ * Blocks of absent modalities are omitted. Components appear in rank order (w/sigma
+ * descending); an empty component has w = 0.
+ */
+gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles);
+
+/* Copy the state out in the canonical layout (host memory, float64). Synchronises `stream`. */
+gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream);
+
+/*
+ * Replace the state from the canonical layout (host memory, float64), rounding each value to
+ * the storage type to nearest, ties to even. I must be 0 or 1 and cpt in [-3, 3], else
+ * GMM_ERR_INVALID_ARG. Synchronises `stream`.
+ */
+gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t gmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGBD_GMM_H */

@@ -1,0 +1,79 @@
+"""MI355X-native RGB-D mixture-of-Gaussians background segmentation.
+
+The per-frame path runs in the HIP library ``libgmm.so`` (C ABI in include/gmm.h); this
+package holds its ctypes binding (``_abi``, same names as the C functions), a small
+convenience wrapper (``Segmenter``), the build step and the seeded synthetic input
+generator (``synth``). Nothing here computes the method on the CPU: if the library is
+missing, every call raises.
+"""
+from __future__ import annotations
+
+from . import _abi
+from ._abi import (GMM_RGB, GMM_DEPTH, GMM_F32, GMM_F16, GMM_BF16, GMM_HOLE_SKIP, GMM_HOLE_AS_VALUE,
+                   GmmError, gmm_config, gmm_config_default, gmm_create, gmm_destroy, gmm_apply_frame,
+                   gmm_fuse, gmm_apply_frame_fused, gmm_last_error, gmm_state_bytes, gmm_state_size,
+                   gmm_read_state, gmm_write_state, gmm_version)
+
+
+def mask_words(npix: int) -> int:
+    """Number of uint64 words of a bit-packed mask of npix pixels."""
+    return (npix + 63) // 64
+
+
+class Segmenter:
+    """One stream's handle plus its output masks (torch tensors on the handle's device)."""
+
+    def __init__(self, width: int, height: int, modalities: int = GMM_RGB | GMM_DEPTH, M: int = 5,
+                 state_dtype: str = "f32", device: int = 0, **params):
+        import torch
+        self.width, self.height, self.M = width, height, M
+        self.modalities = modalities
+        self.npix = width * height
+        self.cfg = gmm_config_default(width, height, modalities, M, state_dtype=_abi.DTYPES[state_dtype],
+                                      device=device, **params)
+        self.handle = gmm_create(self.cfg)
+        dev = torch.device("cuda", device)
+        n = mask_words(self.npix)
+        self.fg_rgb = torch.zeros(n, dtype=torch.int64, device=dev) if modalities & GMM_RGB else None
+        self.fg_depth = torch.zeros(n, dtype=torch.int64, device=dev) if modalities & GMM_DEPTH else None
+        both = (modalities & GMM_RGB) and (modalities & GMM_DEPTH)
+        self.fused = torch.zeros(n, dtype=torch.int64, device=dev) if both else None
+
+    def _pitches(self, rgb, depth):
+        rp = rgb.stride(0) * rgb.element_size() if rgb is not None else 0
+        dp = depth.stride(0) * depth.element_size() if depth is not None else 0
+        return rp, dp
+
+    def apply(self, rgb=None, depth=None, stream=None):
+        rp, dp = self._pitches(rgb, depth)
+        gmm_apply_frame(self.handle, rgb, rp, depth, dp, self.fg_rgb, self.fg_depth, stream)
+        return self.fg_rgb, self.fg_depth
+
+    def apply_fused(self, rgb, depth, stream=None):
+        rp, dp = self._pitches(rgb, depth)
+        gmm_apply_frame_fused(self.handle, rgb, rp, depth, dp, self.fg_rgb, self.fg_depth, self.fused, stream)
+        return self.fg_rgb, self.fg_depth, self.fused
+
+    def fuse(self, fg_rgb, fg_depth, stream=None):
+        gmm_fuse(self.handle, fg_rgb, fg_depth, self.fused, stream)
+        return self.fused
+
+    def read_state(self, stream=None):
+        return gmm_read_state(self.handle, stream)
+
+    def write_state(self, state, stream=None):
+        gmm_write_state(self.handle, state, stream)
+
+    def state_bytes(self) -> int:
+        return gmm_state_bytes(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            gmm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,183 @@
+"""ctypes binding of the C ABI in include/gmm.h (argument marshalling only).
+
+Every function keeps the C name. Device buffers are passed as torch tensors (their
+``data_ptr()``), streams as ``torch.cuda.Stream`` (or None for torch's current stream).
+A non-OK status raises ``GmmError`` carrying ``gmm_last_error()``. There is no fallback:
+if the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmm.so")
+
+GMM_OK = 0
+GMM_ERR_INVALID_ARG = -1
+GMM_ERR_OUT_OF_MEMORY = -2
+GMM_ERR_DEVICE = -3
+GMM_ERR_STATE = -4
+GMM_ERR_UNSUPPORTED = -5
+
+GMM_RGB = 1
+GMM_DEPTH = 2
+GMM_F32, GMM_F16, GMM_BF16 = 0, 1, 2
+GMM_HOLE_SKIP, GMM_HOLE_AS_VALUE = 0, 1
+
+DTYPES = {"f32": GMM_F32, "f16": GMM_F16, "bf16": GMM_BF16}
+
+# every symbol the header declares
+EXPORTS = (
+    "gmm_config_default", "gmm_create", "gmm_destroy", "gmm_apply_frame", "gmm_fuse",
+    "gmm_apply_frame_fused", "gmm_last_error", "gmm_state_bytes", "gmm_state_size",
+    "gmm_read_state", "gmm_write_state", "gmm_version",
+)
+
+
+class GmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gmm status {status}: {msg}")
+        self.status = status
+
+
+class gmm_config(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("modalities", ctypes.c_int32), ("M", ctypes.c_int32),
+        ("alpha", ctypes.c_float), ("k", ctypes.c_float), ("T", ctypes.c_float),
+        ("sigma0", ctypes.c_float * 2), ("var_min", ctypes.c_float * 2),
+        ("w_init", ctypes.c_float),
+        ("hole_policy", ctypes.c_int32), ("state_dtype", ctypes.c_int32), ("device", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(p)
+    H = ctypes.c_void_p
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    sig = {
+        "gmm_config_default": (st, [ctypes.POINTER(gmm_config), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32]),
+        "gmm_create": (st, [ctypes.POINTER(gmm_config), ctypes.POINTER(H)]),
+        "gmm_destroy": (st, [H]),
+        "gmm_apply_frame": (st, [H, vp, i64, vp, i64, vp, vp, vp]),
+        "gmm_fuse": (st, [H, vp, vp, vp, vp]),
+        "gmm_apply_frame_fused": (st, [H, vp, i64, vp, i64, vp, vp, vp, vp]),
+        "gmm_last_error": (ctypes.c_char_p, []),
+        "gmm_state_bytes": (st, [H, ctypes.POINTER(ctypes.c_size_t)]),
+        "gmm_state_size": (st, [H, ctypes.POINTER(ctypes.c_size_t)]),
+        "gmm_read_state": (st, [H, vp, vp]),
+        "gmm_write_state": (st, [H, vp, vp]),
+        "gmm_version": (ctypes.c_int32, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != GMM_OK:
+        msg = load().gmm_last_error()
+        raise GmmError(status, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def gmm_config_default(width: int, height: int, modalities: int = GMM_RGB | GMM_DEPTH, M: int = 5,
+                       **overrides) -> gmm_config:
+    cfg = gmm_config()
+    _check(load().gmm_config_default(ctypes.byref(cfg), width, height, modalities, M))
+    for k, v in overrides.items():
+        if k in ("sigma0", "var_min"):
+            getattr(cfg, k)[0], getattr(cfg, k)[1] = float(v[0]), float(v[1])
+        else:
+            setattr(cfg, k, v)
+    return cfg
+
+
+def gmm_create(cfg: gmm_config) -> int:
+    h = ctypes.c_void_p()
+    _check(load().gmm_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def gmm_destroy(h: Optional[int]):
+    _check(load().gmm_destroy(h))
+
+
+def gmm_apply_frame(h, rgb, rgb_pitch, depth, depth_pitch, fg_rgb, fg_depth, stream=None):
+    _check(load().gmm_apply_frame(h, _ptr(rgb), rgb_pitch, _ptr(depth), depth_pitch, _ptr(fg_rgb),
+                                  _ptr(fg_depth), _stream(stream)))
+
+
+def gmm_fuse(h, fg_rgb, fg_depth, fused, stream=None):
+    _check(load().gmm_fuse(h, _ptr(fg_rgb), _ptr(fg_depth), _ptr(fused), _stream(stream)))
+
+
+def gmm_apply_frame_fused(h, rgb, rgb_pitch, depth, depth_pitch, fg_rgb, fg_depth, fused, stream=None):
+    _check(load().gmm_apply_frame_fused(h, _ptr(rgb), rgb_pitch, _ptr(depth), depth_pitch, _ptr(fg_rgb),
+                                        _ptr(fg_depth), _ptr(fused), _stream(stream)))
+
+
+def gmm_last_error() -> str:
+    m = load().gmm_last_error()
+    return m.decode() if m else ""
+
+
+def gmm_state_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check(load().gmm_state_bytes(h, ctypes.byref(n)))
+    return n.value
+
+
+def gmm_state_size(h) -> int:
+    n = ctypes.c_size_t()
+    _check(load().gmm_state_size(h, ctypes.byref(n)))
+    return n.value
+
+
+def gmm_read_state(h, stream=None):
+    """Returns the canonical float64 state as a NumPy array."""
+    import numpy as np
+    out = np.empty(gmm_state_size(h), dtype=np.float64)
+    _check(load().gmm_read_state(h, out.ctypes.data, _stream(stream)))
+    return out
+
+
+def gmm_write_state(h, state, stream=None):
+    import numpy as np
+    arr = np.ascontiguousarray(state, dtype=np.float64)
+    if arr.size != gmm_state_size(h):
+        raise ValueError(f"state has {arr.size} values, handle needs {gmm_state_size(h)}")
+    _check(load().gmm_write_state(h, arr.ctypes.data, _stream(stream)))
+
+
+def gmm_version() -> int:
+    return load().gmm_version()

@@ -1,0 +1,482 @@
+// The C ABI (include/gmm.h): validation, state ownership, dispatch, state I/O.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gmm.h"
+#include "gmm_internal.hpp"
+
+namespace rgbd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static gmm_status fail(gmm_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+static gmm_status hip_fail(hipError_t e, const char* what) {
+  return fail(GMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Switches to the handle's device for the duration of a call, restoring the caller's.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    ok_ = hipGetDevice(&prev_) == hipSuccess;
+    if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    switched_ = ok_ && prev_ != dev;
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = 0;
+  bool ok_ = false;
+  bool switched_ = false;
+};
+
+static inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Round a double to a binary format with `p` significant bits and smallest normal exponent
+// `emin`, to nearest with ties to even; returns the rounded value as a double.
+static double round_to_format(double v, int p, int emin, double maxv) {
+  if (v == 0.0 || !std::isfinite(v)) return v;
+  int e = 0;
+  (void)std::frexp(v, &e);  // |v| in [2^(e-1), 2^e)
+  const int qexp = std::max(e - p, emin - p + 1);
+  double r = std::ldexp(std::nearbyint(std::ldexp(v, -qexp)), qexp);
+  if (std::fabs(r) > maxv) r = std::copysign(INFINITY, r);
+  return r;
+}
+
+static uint16_t half_bits_exact(double r) {  // r exactly representable as binary16
+  uint16_t sign = std::signbit(r) ? 0x8000u : 0u;
+  double a = std::fabs(r);
+  if (a == 0.0) return sign;
+  if (std::isinf(a)) return sign | 0x7C00u;
+  int e = std::ilogb(a);
+  if (e >= -14) {
+    const uint16_t mant = static_cast<uint16_t>(std::ldexp(a, -e) * 1024.0 - 1024.0);
+    return sign | static_cast<uint16_t>((e + 15) << 10) | mant;
+  }
+  return sign | static_cast<uint16_t>(std::ldexp(a, 24));
+}
+
+static double half_value(uint16_t h) {
+  const double s = (h & 0x8000u) ? -1.0 : 1.0;
+  const int ex = (h >> 10) & 0x1F;
+  const int m = h & 0x3FF;
+  if (ex == 0) return s * std::ldexp(static_cast<double>(m), -24);
+  if (ex == 31) return m ? NAN : s * INFINITY;
+  return s * std::ldexp(1024.0 + m, ex - 25);
+}
+
+static void pack_values(const double* in, void* out, size_t n, int dtype) {
+  if (dtype == GMM_F32) {
+    float* o = static_cast<float*>(out);
+    for (size_t i = 0; i < n; ++i) o[i] = static_cast<float>(in[i]);  // round to nearest even
+  } else if (dtype == GMM_F16) {
+    uint16_t* o = static_cast<uint16_t*>(out);
+    for (size_t i = 0; i < n; ++i) o[i] = half_bits_exact(round_to_format(in[i], 11, -14, 65504.0));
+  } else {
+    uint16_t* o = static_cast<uint16_t*>(out);
+    for (size_t i = 0; i < n; ++i) {
+      const float f = static_cast<float>(round_to_format(in[i], 8, -126, 3.3895313892515355e38));
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      o[i] = static_cast<uint16_t>(u >> 16);
+    }
+  }
+}
+
+static void unpack_values(const void* in, double* out, size_t n, int dtype) {
+  if (dtype == GMM_F32) {
+    const float* s = static_cast<const float*>(in);
+    for (size_t i = 0; i < n; ++i) out[i] = s[i];
+  } else if (dtype == GMM_F16) {
+    const uint16_t* s = static_cast<const uint16_t*>(in);
+    for (size_t i = 0; i < n; ++i) out[i] = half_value(s[i]);
+  } else {
+    const uint16_t* s = static_cast<const uint16_t*>(in);
+    for (size_t i = 0; i < n; ++i) {
+      const uint32_t u = static_cast<uint32_t>(s[i]) << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      out[i] = f;
+    }
+  }
+}
+
+}  // namespace rgbd
+
+using namespace rgbd;
+
+struct gmm_handle {
+  gmm_config cfg;
+  int64_t npix = 0;
+  int64_t stride = 0;       // elements per plane
+  size_t esize = 0;         // bytes per stored value
+  size_t rgb_bytes = 0;     // colour block
+  size_t depth_bytes = 0;   // depth block
+  size_t fuse_bytes = 0;    // List 1 state bytes (padded)
+  void* mem = nullptr;      // one device allocation: [colour][depth][fusion]
+  void* st_rgb = nullptr;
+  void* st_depth = nullptr;
+  uint8_t* fstate = nullptr;
+  hipStream_t last_stream = nullptr;
+  ModelConsts kc{}, kd{};
+};
+
+static bool has_rgb(const gmm_handle* h) { return (h->cfg.modalities & GMM_RGB) != 0; }
+static bool has_depth(const gmm_handle* h) { return (h->cfg.modalities & GMM_DEPTH) != 0; }
+static bool has_both(const gmm_handle* h) { return has_rgb(h) && has_depth(h); }
+
+static gmm_status validate_config(const gmm_config* c) {
+  if (!c) return fail(GMM_ERR_INVALID_ARG, "config is NULL");
+  if (c->width <= 0 || c->height <= 0) return fail(GMM_ERR_INVALID_ARG, "width and height must be > 0");
+  if (static_cast<int64_t>(c->width) * c->height >= (int64_t(1) << 31))
+    return fail(GMM_ERR_INVALID_ARG, "width*height must be < 2^31");
+  if (c->modalities != GMM_RGB && c->modalities != GMM_DEPTH && c->modalities != (GMM_RGB | GMM_DEPTH))
+    return fail(GMM_ERR_INVALID_ARG, "modalities must be GMM_RGB, GMM_DEPTH or both");
+  if (c->M < 1 || c->M > 5) return fail(GMM_ERR_INVALID_ARG, "M must be in 1..5");
+  if (!(c->alpha > 0.f && c->alpha <= 1.f)) return fail(GMM_ERR_INVALID_ARG, "alpha must be in (0, 1]");
+  if (!(c->k > 0.f) || !std::isfinite(c->k)) return fail(GMM_ERR_INVALID_ARG, "k must be > 0");
+  if (!(c->T > 0.f && c->T < 1.f)) return fail(GMM_ERR_INVALID_ARG, "T must be in (0, 1)");
+  for (int i = 0; i < 2; ++i) {
+    if (!(c->sigma0[i] > 0.f) || !std::isfinite(c->sigma0[i]))
+      return fail(GMM_ERR_INVALID_ARG, "sigma0 must be > 0");
+    if (!(c->var_min[i] > 0.f && c->var_min[i] <= c->sigma0[i] * c->sigma0[i]))
+      return fail(GMM_ERR_INVALID_ARG, "var_min must be in (0, sigma0^2]");
+  }
+  if (!(c->w_init > 0.f && c->w_init <= 1.f)) return fail(GMM_ERR_INVALID_ARG, "w_init must be in (0, 1]");
+  if (c->hole_policy != GMM_HOLE_SKIP && c->hole_policy != GMM_HOLE_AS_VALUE)
+    return fail(GMM_ERR_INVALID_ARG, "hole_policy must be GMM_HOLE_SKIP or GMM_HOLE_AS_VALUE");
+  if (c->state_dtype != GMM_F32 && c->state_dtype != GMM_F16 && c->state_dtype != GMM_BF16)
+    return fail(GMM_ERR_INVALID_ARG, "state_dtype must be GMM_F32, GMM_F16 or GMM_BF16");
+  if (c->device < 0) return fail(GMM_ERR_INVALID_ARG, "device must be >= 0");
+  if (!frame_variant_compiled(c->M, c->state_dtype))
+    return fail(GMM_ERR_UNSUPPORTED, "this (M, state dtype) is not compiled");
+  return GMM_OK;
+}
+
+static ModelConsts make_consts(const gmm_config& c, int mod, bool hole_skip) {
+  ModelConsts k{};
+  k.alpha = c.alpha;
+  k.oma = 1.0f - c.alpha;
+  k.k2 = c.k * c.k;
+  k.T = c.T;
+  k.var0 = c.sigma0[mod] * c.sigma0[mod];
+  k.var_min = c.var_min[mod];
+  k.w_init = c.w_init;
+  k.hole_skip = hole_skip ? 1 : 0;
+  return k;
+}
+
+extern "C" {
+
+int32_t gmm_version(void) { return 10000; }
+
+const char* gmm_last_error(void) { return g_last_error.c_str(); }
+
+gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, int32_t modalities,
+                              int32_t M) {
+  if (!cfg) return fail(GMM_ERR_INVALID_ARG, "config is NULL");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->width = width;
+  cfg->height = height;
+  cfg->modalities = modalities;
+  cfg->M = M;
+  cfg->alpha = 0.01f;
+  cfg->k = 2.5f;
+  cfg->T = 0.7f;
+  cfg->sigma0[0] = 30.f;
+  cfg->sigma0[1] = 50.f;
+  cfg->var_min[0] = 9.f;
+  cfg->var_min[1] = 25.f;
+  cfg->w_init = 0.01f;
+  cfg->hole_policy = GMM_HOLE_SKIP;
+  cfg->state_dtype = GMM_F32;
+  cfg->device = 0;
+  return GMM_OK;
+}
+
+gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
+  if (!out) return fail(GMM_ERR_INVALID_ARG, "out is NULL");
+  gmm_status st = validate_config(cfg);
+  if (st != GMM_OK) return st;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (cfg->device >= ndev) return fail(GMM_ERR_INVALID_ARG, "device ordinal out of range");
+
+  gmm_handle* h = new (std::nothrow) gmm_handle();
+  if (!h) return fail(GMM_ERR_OUT_OF_MEMORY, "host allocation of the handle failed");
+  h->cfg = *cfg;
+  h->npix = static_cast<int64_t>(cfg->width) * cfg->height;
+  h->stride = round_up(h->npix, 128);
+  h->esize = dtype_size(cfg->state_dtype);
+  const size_t plane = static_cast<size_t>(h->stride) * h->esize;
+  h->rgb_bytes = has_rgb(h) ? plane * 5 * cfg->M : 0;
+  h->depth_bytes = has_depth(h) ? plane * 3 * cfg->M : 0;
+  h->fuse_bytes = has_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
+  h->kc = make_consts(*cfg, 0, false);
+  h->kd = make_consts(*cfg, 1, cfg->hole_policy == GMM_HOLE_SKIP);
+
+  DeviceGuard g(cfg->device);
+  if (!g.ok()) {
+    delete h;
+    return fail(GMM_ERR_DEVICE, "cannot select the configured device");
+  }
+  const size_t total = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
+  e = hipMalloc(&h->mem, total);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(GMM_ERR_OUT_OF_MEMORY, std::string("hipMalloc of the state failed: ") + hipGetErrorString(e));
+  }
+  uint8_t* base = static_cast<uint8_t*>(h->mem);
+  h->st_rgb = has_rgb(h) ? base : nullptr;
+  h->st_depth = has_depth(h) ? base + h->rgb_bytes : nullptr;
+  h->fstate = has_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
+
+  e = hipSuccess;
+  if (has_rgb(h)) e = launch_init(h->st_rgb, cfg->state_dtype, h->stride, cfg->M, 3, h->kc.var0, nullptr);
+  if (e == hipSuccess && has_depth(h))
+    e = launch_init(h->st_depth, cfg->state_dtype, h->stride, cfg->M, 1, h->kd.var0, nullptr);
+  if (e == hipSuccess && has_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    (void)hipFree(h->mem);
+    delete h;
+    return hip_fail(e, "state initialisation");
+  }
+  *out = h;
+  return GMM_OK;
+}
+
+gmm_status gmm_destroy(gmm_handle* h) {
+  if (!h) return GMM_OK;
+  gmm_status st = GMM_OK;
+  {
+    DeviceGuard g(h->cfg.device);
+    hipError_t e = hipStreamSynchronize(h->last_stream);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize in destroy");
+    e = hipFree(h->mem);
+    if (e != hipSuccess && st == GMM_OK) st = hip_fail(e, "hipFree");
+  }
+  delete h;
+  return st;
+}
+
+gmm_status gmm_state_bytes(const gmm_handle* h, size_t* device_bytes) {
+  if (!h || !device_bytes) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  *device_bytes = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
+  return GMM_OK;
+}
+
+gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles) {
+  if (!h || !n_doubles) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  const size_t n = static_cast<size_t>(h->npix), M = static_cast<size_t>(h->cfg.M);
+  *n_doubles = (has_rgb(h) ? 5 * M * n : 0) + (has_depth(h) ? 3 * M * n : 0) + (has_both(h) ? 2 * n : 0);
+  return GMM_OK;
+}
+
+}  // extern "C"
+
+static gmm_status check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
+                                   const uint16_t* depth, int64_t depth_pitch, uint64_t* fg_rgb,
+                                   uint64_t* fg_depth) {
+  if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
+  const gmm_config& c = h->cfg;
+  if (has_rgb(h)) {
+    if (!rgb || !fg_rgb) return fail(GMM_ERR_INVALID_ARG, "colour handle needs rgb and fg_rgb");
+    if (rgb_pitch < 3 * static_cast<int64_t>(c.width)) return fail(GMM_ERR_INVALID_ARG, "rgb pitch < 3*width");
+    if (reinterpret_cast<uintptr_t>(fg_rgb) % 8) return fail(GMM_ERR_INVALID_ARG, "fg_rgb not 8-byte aligned");
+  } else if (rgb || fg_rgb) {
+    return fail(GMM_ERR_INVALID_ARG, "rgb and fg_rgb must be NULL without the colour modality");
+  }
+  if (has_depth(h)) {
+    if (!depth || !fg_depth) return fail(GMM_ERR_INVALID_ARG, "depth handle needs depth and fg_depth");
+    if (depth_pitch < 2 * static_cast<int64_t>(c.width) || depth_pitch % 2)
+      return fail(GMM_ERR_INVALID_ARG, "depth pitch must be even and >= 2*width");
+    if (reinterpret_cast<uintptr_t>(depth) % 2) return fail(GMM_ERR_INVALID_ARG, "depth not 2-byte aligned");
+    if (reinterpret_cast<uintptr_t>(fg_depth) % 8)
+      return fail(GMM_ERR_INVALID_ARG, "fg_depth not 8-byte aligned");
+  } else if (depth || fg_depth) {
+    return fail(GMM_ERR_INVALID_ARG, "depth and fg_depth must be NULL without the depth modality");
+  }
+  return GMM_OK;
+}
+
+static FrameArgs frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
+                            const uint16_t* depth, int64_t depth_pitch, uint64_t* fg_rgb,
+                            uint64_t* fg_depth, uint64_t* fused) {
+  FrameArgs a{};
+  a.npix = h->npix;
+  a.stride = h->stride;
+  a.width = h->cfg.width;
+  a.rgb = rgb;
+  a.rgb_pitch = rgb_pitch;
+  a.rgb_dense = rgb && rgb_pitch == 3 * static_cast<int64_t>(h->cfg.width) &&
+                reinterpret_cast<uintptr_t>(rgb) % 4 == 0;
+  a.depth = depth;
+  a.depth_pitch = depth_pitch;
+  a.depth_dense = depth && depth_pitch == 2 * static_cast<int64_t>(h->cfg.width);
+  a.st_rgb = h->st_rgb;
+  a.st_depth = h->st_depth;
+  a.fstate = h->fstate;
+  a.fg_rgb = fg_rgb;
+  a.fg_depth = fg_depth;
+  a.fused = fused;
+  a.kc = h->kc;
+  a.kd = h->kd;
+  return a;
+}
+
+extern "C" {
+
+gmm_status gmm_apply_frame(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_bytes,
+                           const uint16_t* depth, int64_t depth_pitch_bytes, uint64_t* fg_rgb,
+                           uint64_t* fg_depth, void* stream) {
+  gmm_status st = check_frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth);
+  if (st != GMM_OK) return st;
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  const FrameArgs a = frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth, nullptr);
+  const int mode = (has_rgb(h) ? kModeRGB : 0) | (has_depth(h) ? kModeDepth : 0);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, mode, s);
+  if (e != hipSuccess) return hip_fail(e, "frame kernel launch");
+  h->last_stream = s;
+  return GMM_OK;
+}
+
+gmm_status gmm_fuse(gmm_handle* h, const uint64_t* fg_rgb, const uint64_t* fg_depth, uint64_t* fused,
+                    void* stream) {
+  if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
+  if (!has_both(h)) return fail(GMM_ERR_STATE, "fusion needs a handle with both modalities");
+  if (!fg_rgb || !fg_depth || !fused) return fail(GMM_ERR_INVALID_ARG, "NULL mask");
+  if ((reinterpret_cast<uintptr_t>(fg_rgb) | reinterpret_cast<uintptr_t>(fg_depth) |
+       reinterpret_cast<uintptr_t>(fused)) % 8)
+    return fail(GMM_ERR_INVALID_ARG, "masks must be 8-byte aligned");
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_fuse(fg_rgb, fg_depth, fused, h->fstate, h->npix, s);
+  if (e != hipSuccess) return hip_fail(e, "fuse kernel launch");
+  h->last_stream = s;
+  return GMM_OK;
+}
+
+gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_bytes,
+                                 const uint16_t* depth, int64_t depth_pitch_bytes,
+                                 uint64_t* fg_rgb, uint64_t* fg_depth, uint64_t* fused,
+                                 void* stream) {
+  if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
+  if (!has_both(h)) return fail(GMM_ERR_STATE, "fusion needs a handle with both modalities");
+  gmm_status st = check_frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth);
+  if (st != GMM_OK) return st;
+  if (!fused || reinterpret_cast<uintptr_t>(fused) % 8)
+    return fail(GMM_ERR_INVALID_ARG, "fused must be a non-NULL 8-byte aligned mask");
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  const FrameArgs a = frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth, fused);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeRGB | kModeDepth | kModeFuse, s);
+  if (e != hipSuccess) return hip_fail(e, "fused frame kernel launch");
+  h->last_stream = s;
+  return GMM_OK;
+}
+
+gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
+  if (!h || !host_out) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t total = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
+  std::vector<uint8_t> raw;
+  try {
+    raw.resize(total);
+  } catch (...) {
+    return fail(GMM_ERR_OUT_OF_MEMORY, "host staging buffer");
+  }
+  hipError_t e = hipMemcpyAsync(raw.data(), h->mem, total, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "state copy to host");
+  const size_t n = static_cast<size_t>(h->npix), M = static_cast<size_t>(h->cfg.M);
+  const size_t plane = static_cast<size_t>(h->stride) * h->esize;
+  double* o = host_out;
+  size_t off = 0;
+  for (int blk = 0; blk < 2; ++blk) {
+    const bool present = blk == 0 ? has_rgb(h) : has_depth(h);
+    if (!present) continue;
+    const int P = blk == 0 ? 5 : 3;
+    for (size_t pl = 0; pl < P * M; ++pl) {
+      unpack_values(raw.data() + off + pl * plane, o, n, h->cfg.state_dtype);
+      o += n;
+    }
+    off += plane * P * M;
+  }
+  if (has_both(h)) {
+    const uint8_t* f = raw.data() + off;
+    for (size_t i = 0; i < n; ++i) o[i] = static_cast<double>((f[i] >> 3) & 1u);
+    o += n;
+    for (size_t i = 0; i < n; ++i) o[i] = static_cast<double>(static_cast<int>(f[i] & 7u) - 3);
+  }
+  return GMM_OK;
+}
+
+gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
+  if (!h || !host_in) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  const size_t n = static_cast<size_t>(h->npix), M = static_cast<size_t>(h->cfg.M);
+  const size_t plane = static_cast<size_t>(h->stride) * h->esize;
+  const size_t total = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
+  std::vector<uint8_t> raw;
+  try {
+    raw.assign(total, 0);
+  } catch (...) {
+    return fail(GMM_ERR_OUT_OF_MEMORY, "host staging buffer");
+  }
+  const double* in = host_in;
+  size_t off = 0;
+  for (int blk = 0; blk < 2; ++blk) {
+    const bool present = blk == 0 ? has_rgb(h) : has_depth(h);
+    if (!present) continue;
+    const int P = blk == 0 ? 5 : 3;
+    for (size_t pl = 0; pl < P * M; ++pl) {
+      pack_values(in, raw.data() + off + pl * plane, n, h->cfg.state_dtype);
+      in += n;
+    }
+    off += plane * P * M;
+  }
+  if (has_both(h)) {
+    uint8_t* f = raw.data() + off;
+    for (size_t i = 0; i < n; ++i) {
+      const double I = in[i], c = in[n + i];
+      if (!(I == 0.0 || I == 1.0)) return fail(GMM_ERR_INVALID_ARG, "fusion bit I must be 0 or 1");
+      if (!(c == std::floor(c) && c >= -3.0 && c <= 3.0))
+        return fail(GMM_ERR_INVALID_ARG, "fusion counter cpt must be an integer in [-3, 3]");
+      f[i] = static_cast<uint8_t>((static_cast<int>(c) + 3) | (static_cast<int>(I) << 3));
+    }
+    for (size_t i = n; i < h->fuse_bytes; ++i) f[i] = static_cast<uint8_t>(kFuseInit);
+  }
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(h->mem, raw.data(), total, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "state copy to device");
+  h->last_stream = s;
+  return GMM_OK;
+}
+
+}  // extern "C"

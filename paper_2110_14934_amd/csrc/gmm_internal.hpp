@@ -1,0 +1,50 @@
+// Host-side internals shared by the ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "gmm.h"
+#include "gmm_device.hpp"
+
+namespace rgbd {
+
+// Everything one frame-kernel launch needs for one stream.
+struct FrameArgs {
+  int64_t npix;
+  int64_t stride;          // elements between consecutive state planes (npix rounded up to 64)
+  int32_t width;
+  int32_t rgb_dense;       // rgb rows are contiguous (pitch == 3*width) and 4-byte aligned
+  int32_t depth_dense;     // depth rows are contiguous (pitch == 2*width)
+  const uint8_t* rgb;
+  int64_t rgb_pitch;
+  const uint16_t* depth;
+  int64_t depth_pitch;
+  void* st_rgb;            // colour state block: 5*M planes
+  void* st_depth;          // depth state block: 3*M planes
+  uint8_t* fstate;         // List 1 state bytes
+  uint64_t* fg_rgb;
+  uint64_t* fg_depth;
+  uint64_t* fused;
+  ModelConsts kc;          // colour constants
+  ModelConsts kd;          // depth constants
+};
+
+enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4 };
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStream_t s);
+hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, uint8_t* fstate,
+                       int64_t npix, hipStream_t s);
+hipError_t launch_init(void* st, int dtype, int64_t stride, int M, int C, float var0, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+
+bool frame_variant_compiled(int M, int dtype);
+
+inline size_t dtype_size(int dtype) { return dtype == GMM_F32 ? 4 : 2; }
+
+void set_error(const std::string& msg);
+
+}  // namespace rgbd

@@ -1,0 +1,208 @@
+// Per-frame kernels of one stream: colour and/or depth mixture step, optional List 1 fusion.
+//
+// Mapping: one lane per pixel of the row-major frame; a wave covers 64 consecutive pixels, so
+// its foreground bits form exactly one uint64 word of the output mask (one ballot, one store).
+// The interleaved RGB8 input of a wave (192 contiguous bytes when rows are dense) is staged
+// through LDS with 48 dword loads and de-interleaved on chip - the structure-of-arrays split of
+// the colour image done without a separate pass. State planes are structure-of-arrays, so every
+// state load and store of a wave is one contiguous 256-byte (fp32) segment.
+#include <hip/hip_runtime.h>
+
+#include "gmm_device.hpp"
+#include "gmm_internal.hpp"
+
+namespace rgbd {
+
+__device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, int64_t p, int64_t wave_base,
+                                               int lane, uint32_t* lds_wave, bool valid,
+                                               float (&x)[3]) {
+  const bool fast = a.rgb_dense && (wave_base + kWave <= a.npix);  // uniform over the wave
+  if (fast) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.rgb + 3 * wave_base);
+    if (lane < 48) lds_wave[lane] = src[lane];
+    wave_lds_sync();
+    const uint8_t* b = reinterpret_cast<const uint8_t*>(lds_wave) + 3 * lane;
+    x[0] = b[0];
+    x[1] = b[1];
+    x[2] = b[2];
+    wave_lds_sync();
+  } else if (valid) {
+    const int32_t y = static_cast<int32_t>(p / a.width);
+    const int32_t xx = static_cast<int32_t>(p - static_cast<int64_t>(y) * a.width);
+    const uint8_t* b = a.rgb + static_cast<int64_t>(y) * a.rgb_pitch + 3 * xx;
+    x[0] = b[0];
+    x[1] = b[1];
+    x[2] = b[2];
+  } else {
+    x[0] = x[1] = x[2] = 0.f;
+  }
+}
+
+__device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, int64_t p) {
+  if (a.depth_dense) return static_cast<float>(a.depth[p]);
+  const int32_t y = static_cast<int32_t>(p / a.width);
+  const int32_t xx = static_cast<int32_t>(p - static_cast<int64_t>(y) * a.width);
+  const uint16_t* row = reinterpret_cast<const uint16_t*>(
+      reinterpret_cast<const uint8_t*>(a.depth) + static_cast<int64_t>(y) * a.depth_pitch);
+  return static_cast<float>(row[xx]);
+}
+
+// One stream, one frame. MODE is a combination of kModeRGB, kModeDepth, kModeFuse.
+template <int M, typename S, int MODE>
+__global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
+  __shared__ uint32_t lds[kWavesPerBlock][48];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t wave_base = p - lane;
+  const bool valid = p < a.npix;
+
+  bool fgc = false, fgd = false;
+  if constexpr ((MODE & kModeRGB) != 0) {
+    float x[3];
+    load_rgb_pixel(a, p, wave_base, lane, lds[wv], valid, x);
+    if (valid) {
+      Mix<M, 3> m;
+      S* st = static_cast<S*>(a.st_rgb);
+      load_mix<M, 3, S>(m, st, a.stride, p);
+      fgc = mix_step<M, 3>(m, x, a.kc);
+      store_mix<M, 3, S>(m, st, a.stride, p);
+    }
+    const uint64_t bits = __ballot(fgc);
+    if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
+  }
+  if constexpr ((MODE & kModeDepth) != 0) {
+    if (valid) {
+      const float xd = load_depth_pixel(a, p);
+      if (!(a.kd.hole_skip && xd == 0.f)) {
+        Mix<M, 1> m;
+        S* st = static_cast<S*>(a.st_depth);
+        load_mix<M, 1, S>(m, st, a.stride, p);
+        const float x1[1] = {xd};
+        fgd = mix_step<M, 1>(m, x1, a.kd);
+        store_mix<M, 1, S>(m, st, a.stride, p);
+      }
+    }
+    const uint64_t bits = __ballot(fgd);
+    if (lane == 0 && valid) a.fg_depth[wave_base >> 6] = bits;
+  }
+  if constexpr ((MODE & kModeFuse) != 0) {
+    bool fgf = false;
+    if (valid) {
+      const uint32_t st = fuse_transition(a.fstate[p], fgc, fgd);
+      a.fstate[p] = static_cast<uint8_t>(st);
+      fgf = (st >> 3) & 1u;
+    }
+    const uint64_t bits = __ballot(fgf);
+    if (lane == 0 && valid) a.fused[wave_base >> 6] = bits;
+  }
+}
+
+// Standalone List 1 over two given masks.
+__global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict__ fr,
+                                                      const uint64_t* __restrict__ fd,
+                                                      uint64_t* __restrict__ out,
+                                                      uint8_t* __restrict__ fstate, int64_t npix) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t word = (p - lane) >> 6;
+  const bool valid = p < npix;
+  bool fgf = false;
+  if (valid) {
+    const bool r = (fr[word] >> lane) & 1ull;
+    const bool d = (fd[word] >> lane) & 1ull;
+    const uint32_t st = fuse_transition(fstate[p], r, d);
+    fstate[p] = static_cast<uint8_t>(st);
+    fgf = (st >> 3) & 1u;
+  }
+  const uint64_t bits = __ballot(fgf);
+  if (lane == 0 && valid) out[word] = bits;
+}
+
+// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks).
+template <typename S>
+__global__ void __launch_bounds__(kBlock) init_kernel(S* st, int64_t stride, int M, int C,
+                                                      float var0) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t total = static_cast<int64_t>(C + 2) * M * stride;
+  if (i >= total) return;
+  const int64_t plane = i / stride;
+  const int64_t param = plane / M;
+  st[i] = Storage<S>::pack(param == C ? var0 : 0.f);
+}
+
+__global__ void __launch_bounds__(kBlock) fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---- dispatch ----------------------------------------------------------------------------
+
+static inline dim3 grid_for(int64_t n) {
+  return dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock));
+}
+
+template <int M, typename S>
+static hipError_t launch_frame_ms(const FrameArgs& a, int mode, hipStream_t s) {
+  const dim3 g = grid_for(a.npix), b(kBlock);
+  switch (mode) {
+    case kModeRGB: frame_kernel<M, S, kModeRGB><<<g, b, 0, s>>>(a); break;
+    case kModeDepth: frame_kernel<M, S, kModeDepth><<<g, b, 0, s>>>(a); break;
+    case kModeRGB | kModeDepth: frame_kernel<M, S, kModeRGB | kModeDepth><<<g, b, 0, s>>>(a); break;
+    case kModeRGB | kModeDepth | kModeFuse:
+      frame_kernel<M, S, kModeRGB | kModeDepth | kModeFuse><<<g, b, 0, s>>>(a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_frame_s(const FrameArgs& a, int M, int mode, hipStream_t s) {
+  switch (M) {
+    case 1: return launch_frame_ms<1, S>(a, mode, s);
+    case 2: return launch_frame_ms<2, S>(a, mode, s);
+    case 3: return launch_frame_ms<3, S>(a, mode, s);
+    case 4: return launch_frame_ms<4, S>(a, mode, s);
+    case 5: return launch_frame_ms<5, S>(a, mode, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool frame_variant_compiled(int M, int dtype) {
+  return M >= 1 && M <= 5 && (dtype == GMM_F32 || dtype == GMM_F16 || dtype == GMM_BF16);
+}
+
+hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStream_t s) {
+  switch (dtype) {
+    case GMM_F32: return launch_frame_s<float>(a, M, mode, s);
+    case GMM_F16: return launch_frame_s<f16s>(a, M, mode, s);
+    case GMM_BF16: return launch_frame_s<bf16s>(a, M, mode, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, uint8_t* fstate,
+                       int64_t npix, hipStream_t s) {
+  fuse_kernel<<<grid_for(npix), dim3(kBlock), 0, s>>>(fr, fd, out, fstate, npix);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(void* st, int dtype, int64_t stride, int M, int C, float var0, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(C + 2) * M * stride;
+  const dim3 g = grid_for(total), b(kBlock);
+  switch (dtype) {
+    case GMM_F32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float*>(st), stride, M, C, var0); break;
+    case GMM_F16: init_kernel<f16s><<<g, b, 0, s>>>(static_cast<f16s*>(st), stride, M, C, var0); break;
+    case GMM_BF16: init_kernel<bf16s><<<g, b, 0, s>>>(static_cast<bf16s*>(st), stride, M, C, var0); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
+  fill_u8_kernel<<<grid_for(n), dim3(kBlock), 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace rgbd

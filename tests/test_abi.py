@@ -1,0 +1,100 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol, and rejects bad
+arguments with the documented status before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2110_14934_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2110_14934_amd.build import build
+        build()
+    return _abi.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    assert set(names) == set(_abi.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (gmm_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+
+
+def test_version_and_defaults(lib):
+    assert _abi.gmm_version() == 10000
+    cfg = _abi.gmm_config_default(640, 480, _abi.GMM_RGB | _abi.GMM_DEPTH, 5)
+    assert (cfg.width, cfg.height, cfg.M) == (640, 480, 5)
+    assert cfg.alpha == pytest.approx(0.01) and cfg.k == 2.5 and cfg.T == pytest.approx(0.7)
+    assert list(cfg.sigma0) == [30.0, 50.0] and list(cfg.var_min) == [9.0, 25.0]
+    assert cfg.w_init == pytest.approx(0.01)
+    assert cfg.hole_policy == _abi.GMM_HOLE_SKIP and cfg.state_dtype == _abi.GMM_F32
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("width", 0, "width"), ("height", -3, "width"), ("modalities", 0, "modalities"),
+    ("modalities", 4, "modalities"), ("M", 0, "M must"), ("M", 6, "M must"),
+    ("alpha", 0.0, "alpha"), ("alpha", 1.5, "alpha"), ("k", 0.0, "k must"), ("T", 1.0, "T must"),
+    ("T", 0.0, "T must"), ("w_init", 0.0, "w_init"), ("hole_policy", 7, "hole_policy"),
+    ("state_dtype", 9, "state_dtype"), ("device", -1, "device"),
+])
+def test_create_rejects_bad_config_without_device(lib, field, value, needle):
+    cfg = _abi.gmm_config_default(64, 48, 3, 3)
+    setattr(cfg, field, value)
+    with pytest.raises(_abi.GmmError) as e:
+        _abi.gmm_create(cfg)
+    assert e.value.status == _abi.GMM_ERR_INVALID_ARG
+    assert needle in str(e.value)
+
+
+def test_create_rejects_bad_sigma_and_floor(lib):
+    cfg = _abi.gmm_config_default(64, 48, 3, 3)
+    cfg.var_min[1] = 2501.0   # above sigma0^2 of depth
+    with pytest.raises(_abi.GmmError) as e:
+        _abi.gmm_create(cfg)
+    assert "var_min" in str(e.value)
+    cfg = _abi.gmm_config_default(64, 48, 3, 3)
+    cfg.sigma0[0] = 0.0
+    with pytest.raises(_abi.GmmError):
+        _abi.gmm_create(cfg)
+    cfg = _abi.gmm_config_default(70000, 40000, 3, 3)
+    with pytest.raises(_abi.GmmError) as e:
+        _abi.gmm_create(cfg)
+    assert "2^31" in str(e.value)
+
+
+def test_null_arguments(lib):
+    assert lib.gmm_destroy(None) == _abi.GMM_OK
+    assert lib.gmm_apply_frame(None, None, 0, None, 0, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert "NULL" in _abi.gmm_last_error()
+    assert lib.gmm_fuse(None, None, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_apply_frame_fused(None, None, 0, None, 0, None, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_read_state(None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_write_state(None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert lib.gmm_state_size(None, ctypes.byref(n)) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_state_bytes(None, ctypes.byref(n)) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_create(None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_config_default(None, 1, 1, 1, 1) == _abi.GMM_ERR_INVALID_ARG
+
+
+def test_config_struct_layout_matches_header(lib):
+    # 4 ints, 3 floats, 2x2 floats, 1 float, 3 ints = 15 four-byte fields
+    assert ctypes.sizeof(_abi.gmm_config) == 15 * 4
