@@ -1,0 +1,255 @@
+"""Throughput of the per-frame RGB-D mixture path on one MI355X.
+
+A step is one frame of the workload through the whole per-frame path (colour and depth mixture
+update and classification, bit-packed masks, List 1 fusion) in one fused launch per stream.
+Default workload: one 640x480 RGB-D stream, M=5, fp32 state, the 300-frame synthetic clip
+(gain ramp over frames 100-150, three moving boxes, 5% depth holes), frames resident in HBM
+before timing starts. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_frame_kernel_plain-640x480.json")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2110_14934_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_frame(npix: int, holes: float, M: int, esize: int) -> float:
+    """Algorithmic HBM bytes of one fused launch on one paired stream.
+
+    Colour: read and rewrite all 5*M state values, read 3 input bytes, write 1 mask bit.
+    Depth: the same with 3*M values and 2 input bytes; a hole pixel reads its 2 input bytes
+    but leaves its state untouched. Fusion: read and write the state byte, write 1 fused bit."""
+    colour = npix * (2 * 5 * M * esize + 3 + 1 / 8)
+    depth = npix * (2 + 1 / 8) + (npix - holes) * (2 * 3 * M * esize)
+    fusion = npix * (2 + 1 / 8)
+    return colour + depth + fusion
+
+
+def alg_bytes_hint(npix: int, M: int, esize: int) -> float:
+    return bytes_per_frame(npix, 0.0, M, esize)
+
+
+def cpu_baseline(wl, seconds: float):
+    """The FP64 oracle on the host: whole frames of the same stream until `seconds` elapse."""
+    import numpy as np
+    from oracle import MixParams, MixtureOracle, FusionOracle
+    from paper_2110_14934_amd.synth import Stream
+    spec, mix = wl.streams[0], wl.mix
+    st = Stream(spec)
+    n = spec.npix
+    col = MixtureOracle(MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_rgb, mix.var_min_rgb, mix.w_init), 3, n)
+    dep = MixtureOracle(MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_depth, mix.var_min_depth,
+                                  mix.w_init, hole_skip=True), 1, n)
+    fus = FusionOracle(n)
+    elapsed, frames = 0.0, 0
+    while elapsed < seconds and frames < wl.frames:
+        rgb = st.rgb(frames).reshape(-1, 3).numpy()
+        dep_f = st.depth(frames).reshape(-1).numpy()
+        t0 = time.perf_counter()
+        ic = col.step(rgb)
+        idd = dep.step(dep_f)
+        fus.step(ic.fg, idd.fg)
+        elapsed += time.perf_counter() - t0
+        frames += 1
+    pu = 2 * n * frames
+    return {"value": pu / elapsed, "unit": "pixel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"frames 0-{frames - 1} of the {spec.width}x{spec.height} RGB-D stream, all {n} pixels, "
+                      f"colour+depth+fusion, float64 NumPy on one host core ({elapsed:.1f} s)",
+            "host_cpus": os.cpu_count()}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="plain-640x480")
+    ap.add_argument("--mode", choices=("graph", "eager"), default="graph",
+                    help="graph: replay a captured hipGraph of the whole clip; eager: one launch per call")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--host-frames", type=int, default=0, metavar="N",
+                    help="build N distinct frames on the host and cycle them (few GPU dispatches besides the "
+                         "path itself, for counter collection); default: the whole clip generated on the GPU")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one device copy of MIB MiB (for counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        return 2
+    if args.workload != "plain-640x480":
+        print("only the plain-640x480 workload is benchmarked by this script", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2110_14934_amd import _abi, Segmenter, GMM_RGB, GMM_DEPTH
+    from paper_2110_14934_amd.synth import Stream, workload
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2110_14934_amd.build import build
+        build()
+    dev = torch.device("cuda", 0)
+    wl = workload(args.workload)
+    spec, mix = wl.streams[0], wl.mix
+    st = Stream(spec)
+    F = wl.frames
+    n = spec.npix
+
+    # inputs resident in HBM before timing
+    if args.host_frames:
+        F = args.host_frames
+        rgbs = [st.rgb(t).to(dev) for t in range(F)]
+        deps = [st.depth(t).to(dev) for t in range(F)]
+    else:
+        rgbs = [st.rgb(t, device=dev) for t in range(F)]
+        deps = [st.depth(t, device=dev) for t in range(F)]
+    holes = torch.stack([(d == 0).sum() for d in deps]).to(torch.float64).cpu().numpy()
+    torch.cuda.synchronize()
+    print(f"[bench] {F} frames of {spec.width}x{spec.height} resident on {torch.cuda.get_device_name(0)}",
+          file=sys.stderr, flush=True)
+
+    seg = Segmenter(spec.width, spec.height, GMM_RGB | GMM_DEPTH, mix.M, state_dtype=wl.state_dtype)
+    stream = torch.cuda.Stream()
+    K, W = args.steps, args.warmup
+
+    with torch.cuda.stream(stream):
+        for t in range(W):
+            seg.apply_fused(rgbs[t % F], deps[t % F], stream)
+    stream.synchronize()
+
+    graph = None
+    if args.mode == "graph":
+        # one graph node per frame of the clip, in order, starting where the warm-up ended
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            for i in range(F):
+                t = (W + i) % F
+                seg.apply_fused(rgbs[t], deps[t], torch.cuda.current_stream())
+        # capture does not execute: restore the state the warm-up left
+        torch.cuda.synchronize()
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes MIB MiB each
+        torch.cuda.synchronize()
+        del src, dst
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    if graph is not None:
+        reps, rem = divmod(K, F)  # the graph holds one node per clip frame
+        if rem:
+            raise SystemExit(f"--steps must be a multiple of the clip length {F} in graph mode")
+        with torch.cuda.stream(stream):
+            for _ in range(reps):
+                graph.replay()
+    else:
+        with torch.cuda.stream(stream):
+            for i in range(K):
+                t = (W + i) % F
+                seg.apply_fused(rgbs[t], deps[t], stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / K
+    print(f"[bench] timed {K} steps: {ms_total:.2f} ms", file=sys.stderr, flush=True)
+
+    # practical read+write ceiling: a device copy moving the same bytes as one launch
+    copy_gbs = None
+    if not args.host_frames:
+        half = int(alg_bytes_hint(n, mix.M, 4 if wl.state_dtype == "f32" else 2) // 2) // 4 * 4
+        src = torch.empty(half // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                dst.copy_(src)
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            for _ in range(200):
+                dst.copy_(src)
+            c1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2 * half / (c0.elapsed_time(c1) / 200 / 1e3) / 1e9
+        del src, dst
+
+    pu_step = 2 * n
+    value = pu_step * K / (ms_total / 1e3)
+    idx = [(W + i) % F for i in range(K)]
+    mean_holes = float(holes[idx].mean())
+    esize = 4 if wl.state_dtype == "f32" else 2
+    alg_bytes = bytes_per_frame(n, mean_holes, mix.M, esize)
+    achieved = alg_bytes / (ms_step / 1e3) / 1e9
+
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        rec = json.load(open(PROFILE_TRAFFIC))
+        if rec.get("kernel_source_digest") == kernel_source_digest():
+            traffic = rec.get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": "RGBD GMM pixel-updates/s",
+        "value": value,
+        "unit": "pixel-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Kinect-shaped RGB-D stream; the paper's captures are not available)",
+        "config": {"workload": args.workload, "streams": 1, "width": spec.width, "height": spec.height,
+                   "M": mix.M, "modalities": "rgb+depth+fusion", "state_dtype": wl.state_dtype,
+                   "clip_frames": F, "launch": args.mode},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "rgbd::frame_kernel<5, float, 7>",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": ms_step * 1e3,
+                     "device_copy_same_bytes_gbs": copy_gbs},
+        "frames_per_s": 1e3 / ms_step,
+        "paper_context": {"value": 2 * 640 * 480 * 30, "unit": "pixel-updates/s",
+                          "note": "30 fps VGA colour+depth end to end incl. transfers, unnamed GPU (Sec. V.B)"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    seg.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -64,7 +64,7 @@ enum { GMM_HOLE_SKIP = 0,      /* state untouched, pixel classified background  
  * background weight threshold T. Index 0 of the two-element arrays is colour, 1 is depth.
  */
 typedef struct {
-  int32_t width, height;   /* > 0, width*height < 2^31                                    */
+  int32_t width, height;   /* > 0, width*height < 2^29 (32-bit byte offsets in the kernels) */
   int32_t modalities;      /* GMM_RGB, GMM_DEPTH or both                                    */
   int32_t M;               /* 1..5                                                          */
   float alpha;             /* (0, 1]                                                        */

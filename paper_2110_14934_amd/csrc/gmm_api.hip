@@ -144,8 +144,8 @@ static bool has_both(const gmm_handle* h) { return has_rgb(h) && has_depth(h); }
 static gmm_status validate_config(const gmm_config* c) {
   if (!c) return fail(GMM_ERR_INVALID_ARG, "config is NULL");
   if (c->width <= 0 || c->height <= 0) return fail(GMM_ERR_INVALID_ARG, "width and height must be > 0");
-  if (static_cast<int64_t>(c->width) * c->height >= (int64_t(1) << 31))
-    return fail(GMM_ERR_INVALID_ARG, "width*height must be < 2^31");
+  if (static_cast<int64_t>(c->width) * c->height >= (int64_t(1) << 29))
+    return fail(GMM_ERR_INVALID_ARG, "width*height must be < 2^29");
   if (c->modalities != GMM_RGB && c->modalities != GMM_DEPTH && c->modalities != (GMM_RGB | GMM_DEPTH))
     return fail(GMM_ERR_INVALID_ARG, "modalities must be GMM_RGB, GMM_DEPTH or both");
   if (c->M < 1 || c->M > 5) return fail(GMM_ERR_INVALID_ARG, "M must be in 1..5");
@@ -229,6 +229,10 @@ gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
   h->rgb_bytes = has_rgb(h) ? plane * 5 * cfg->M : 0;
   h->depth_bytes = has_depth(h) ? plane * 3 * cfg->M : 0;
   h->fuse_bytes = has_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
+  if (std::max(h->rgb_bytes, h->depth_bytes) > 0xFFFFFFFFull) {
+    delete h;
+    return fail(GMM_ERR_INVALID_ARG, "one modality's state must stay below 4 GiB (too many pixels for this M)");
+  }
   h->kc = make_consts(*cfg, 0, false);
   h->kd = make_consts(*cfg, 1, cfg->hole_policy == GMM_HOLE_SKIP);
 

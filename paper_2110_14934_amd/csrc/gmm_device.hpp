@@ -65,32 +65,77 @@ struct Mix {
   float w[M];
 };
 
-// Plane order inside one modality's state block: mu channel 0..C-1, var, w; each plane holds
-// M rank-major sub-planes of `stride` pixels.
+// One modality's state block as a buffer resource. Plane order inside the block: mu channel
+// 0..C-1, var, w; each plane holds M rank-major sub-planes of `stride` pixels. A lane's byte
+// offset lives in one VGPR; the plane offset is a wave-uniform scalar (soffset), so every state
+// access is a single buffer instruction with no per-lane address arithmetic. The range checked
+// by the hardware (num_records) is the whole block - on gfx950 the scalar offset counts toward
+// it - so an access outside the block reads 0 and drops its write instead of touching other
+// memory. The host keeps every block below 4 GiB.
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
+
+struct StateBlock {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t plane_bytes;
+};
+
+__device__ __forceinline__ StateBlock make_block(void* base, int64_t stride, int esize, int planes) {
+  const uint32_t pb = static_cast<uint32_t>(stride * esize);
+  const uint32_t total = pb * static_cast<uint32_t>(planes);
+  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(total), kRsrcWord3), pb};
+}
+
+template <typename S> struct BufIO;
+template <> struct BufIO<float> {
+  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off, uint32_t so) {
+    // the b32 builtins move raw 32-bit words: reinterpret, never convert
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, off, so, 0));
+  }
+  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, uint32_t so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.rsrc, off, so, 0);
+  }
+};
+template <> struct BufIO<f16s> {
+  static __device__ __forceinline__ f16s ld(const StateBlock& b, uint32_t off, uint32_t so) {
+    return f16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, so, 0)};
+  }
+  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, uint32_t so, f16s v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v.b, b.rsrc, off, so, 0);
+  }
+};
+template <> struct BufIO<bf16s> {
+  static __device__ __forceinline__ bf16s ld(const StateBlock& b, uint32_t off, uint32_t so) {
+    return bf16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, so, 0)};
+  }
+  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, uint32_t so, bf16s v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v.b, b.rsrc, off, so, 0);
+  }
+};
+
 template <int M, int C, typename S>
-__device__ __forceinline__ void load_mix(Mix<M, C>& m, const S* __restrict__ base, int64_t stride,
-                                         int64_t p) {
+__device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+  const uint32_t off = p * static_cast<uint32_t>(sizeof(S));
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int r = 0; r < M; ++r) m.mu[c][r] = Storage<S>::load(base[(c * M + r) * stride + p]);
+    for (int r = 0; r < M; ++r) m.mu[c][r] = Storage<S>::load(BufIO<S>::ld(b, off, (c * M + r) * b.plane_bytes));
 #pragma unroll
-  for (int r = 0; r < M; ++r) m.var[r] = Storage<S>::load(base[(C * M + r) * stride + p]);
+  for (int r = 0; r < M; ++r) m.var[r] = Storage<S>::load(BufIO<S>::ld(b, off, (C * M + r) * b.plane_bytes));
 #pragma unroll
-  for (int r = 0; r < M; ++r) m.w[r] = Storage<S>::load(base[((C + 1) * M + r) * stride + p]);
+  for (int r = 0; r < M; ++r) m.w[r] = Storage<S>::load(BufIO<S>::ld(b, off, ((C + 1) * M + r) * b.plane_bytes));
 }
 
 template <int M, int C, typename S>
-__device__ __forceinline__ void store_mix(const Mix<M, C>& m, S* __restrict__ base, int64_t stride,
-                                          int64_t p) {
+__device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+  const uint32_t off = p * static_cast<uint32_t>(sizeof(S));
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int r = 0; r < M; ++r) base[(c * M + r) * stride + p] = Storage<S>::pack(m.mu[c][r]);
+    for (int r = 0; r < M; ++r) BufIO<S>::st(b, off, (c * M + r) * b.plane_bytes, Storage<S>::pack(m.mu[c][r]));
 #pragma unroll
-  for (int r = 0; r < M; ++r) base[(C * M + r) * stride + p] = Storage<S>::pack(m.var[r]);
+  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off, (C * M + r) * b.plane_bytes, Storage<S>::pack(m.var[r]));
 #pragma unroll
-  for (int r = 0; r < M; ++r) base[((C + 1) * M + r) * stride + p] = Storage<S>::pack(m.w[r]);
+  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off, ((C + 1) * M + r) * b.plane_bytes, Storage<S>::pack(m.w[r]));
 }
 
 template <typename T>
@@ -120,27 +165,38 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       const float t = x[c] - s.mu[c][r];
       d2 = fmaf(t, t, d2);
     }
-    const bool hit = (s.w[r] > 0.f) && (d2 < k.k2 * s.var[r]);
-    j = (j == M && hit) ? r : j;
+    const bool hit = (s.w[r] > 0.f) & (d2 < k.k2 * s.var[r]);  // no short-circuit: no branch
+    j = ((j == M) & hit) ? r : j;
   }
   const bool matched = j < M;
 
-  // weight decay, and the matched component's mean and variance
+  // weight decay; the matched component is gathered, updated once and scattered back
+  // (branch-free: every rank is a select, no per-rank divergent region)
+  float mj[C], vj = s.var[0];
+#pragma unroll
+  for (int c = 0; c < C; ++c) mj[c] = s.mu[c][0];
+#pragma unroll
+  for (int r = 1; r < M; ++r) {
+    const bool isj = (r == j);
+    vj = isj ? s.var[r] : vj;
+#pragma unroll
+    for (int c = 0; c < C; ++c) mj[c] = isj ? s.mu[c][r] : mj[c];
+  }
+  float d2n = 0.f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
+    const float t = x[c] - mj[c];
+    d2n = fmaf(t, t, d2n);
+  }
+  vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     const bool isj = (r == j);
     s.w[r] = fmaf(k.oma, s.w[r], isj ? k.alpha : 0.f);
-    if (isj) {
-      float d2 = 0.f;
+    s.var[r] = isj ? vj : s.var[r];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const float m = fmaf(k.oma, s.mu[c][r], k.alpha * x[c]);
-        s.mu[c][r] = m;
-        const float t = x[c] - m;
-        d2 = fmaf(t, t, d2);
-      }
-      s.var[r] = fmaxf(k.var_min, fmaf(k.oma, s.var[r], k.alpha * d2));
-    }
+    for (int c = 0; c < C; ++c) s.mu[c][r] = isj ? mj[c] : s.mu[c][r];
   }
   // no match: the least probable (last-ranked) component is replaced
   if (!matched) {

@@ -13,12 +13,12 @@
 
 namespace rgbd {
 
-__device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, int64_t p, int64_t wave_base,
+__device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base,
                                                int lane, uint32_t* lds_wave, bool valid,
                                                float (&x)[3]) {
   const bool fast = a.rgb_dense && (wave_base + kWave <= a.npix);  // uniform over the wave
   if (fast) {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.rgb + 3 * wave_base);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.rgb + 3 * static_cast<uint64_t>(wave_base));
     if (lane < 48) lds_wave[lane] = src[lane];
     wave_lds_sync();
     const uint8_t* b = reinterpret_cast<const uint8_t*>(lds_wave) + 3 * lane;
@@ -27,8 +27,8 @@ __device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, int64_t p, in
     x[2] = b[2];
     wave_lds_sync();
   } else if (valid) {
-    const int32_t y = static_cast<int32_t>(p / a.width);
-    const int32_t xx = static_cast<int32_t>(p - static_cast<int64_t>(y) * a.width);
+    const uint32_t y = p / static_cast<uint32_t>(a.width);
+    const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
     const uint8_t* b = a.rgb + static_cast<int64_t>(y) * a.rgb_pitch + 3 * xx;
     x[0] = b[0];
     x[1] = b[1];
@@ -38,10 +38,10 @@ __device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, int64_t p, in
   }
 }
 
-__device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, int64_t p) {
+__device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p) {
   if (a.depth_dense) return static_cast<float>(a.depth[p]);
-  const int32_t y = static_cast<int32_t>(p / a.width);
-  const int32_t xx = static_cast<int32_t>(p - static_cast<int64_t>(y) * a.width);
+  const uint32_t y = p / static_cast<uint32_t>(a.width);
+  const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
   const uint16_t* row = reinterpret_cast<const uint16_t*>(
       reinterpret_cast<const uint8_t*>(a.depth) + static_cast<int64_t>(y) * a.depth_pitch);
   return static_cast<float>(row[xx]);
@@ -53,8 +53,8 @@ __global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
   __shared__ uint32_t lds[kWavesPerBlock][48];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t wave_base = p - lane;
+  const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t wave_base = p - lane;
   const bool valid = p < a.npix;
 
   bool fgc = false, fgd = false;
@@ -63,10 +63,10 @@ __global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
     load_rgb_pixel(a, p, wave_base, lane, lds[wv], valid, x);
     if (valid) {
       Mix<M, 3> m;
-      S* st = static_cast<S*>(a.st_rgb);
-      load_mix<M, 3, S>(m, st, a.stride, p);
+      const StateBlock blk = make_block(a.st_rgb, a.stride, sizeof(S), 5 * M);
+      load_mix<M, 3, S>(m, blk, p);
       fgc = mix_step<M, 3>(m, x, a.kc);
-      store_mix<M, 3, S>(m, st, a.stride, p);
+      store_mix<M, 3, S>(m, blk, p);
     }
     const uint64_t bits = __ballot(fgc);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
@@ -76,11 +76,11 @@ __global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
       const float xd = load_depth_pixel(a, p);
       if (!(a.kd.hole_skip && xd == 0.f)) {
         Mix<M, 1> m;
-        S* st = static_cast<S*>(a.st_depth);
-        load_mix<M, 1, S>(m, st, a.stride, p);
+        const StateBlock blk = make_block(a.st_depth, a.stride, sizeof(S), 3 * M);
+        load_mix<M, 1, S>(m, blk, p);
         const float x1[1] = {xd};
         fgd = mix_step<M, 1>(m, x1, a.kd);
-        store_mix<M, 1, S>(m, st, a.stride, p);
+        store_mix<M, 1, S>(m, blk, p);
       }
     }
     const uint64_t bits = __ballot(fgd);

@@ -74,10 +74,10 @@ def test_create_rejects_bad_sigma_and_floor(lib):
     cfg.sigma0[0] = 0.0
     with pytest.raises(_abi.GmmError):
         _abi.gmm_create(cfg)
-    cfg = _abi.gmm_config_default(70000, 40000, 3, 3)
+    cfg = _abi.gmm_config_default(30000, 20000, 3, 3)
     with pytest.raises(_abi.GmmError) as e:
         _abi.gmm_create(cfg)
-    assert "2^31" in str(e.value)
+    assert "2^29" in str(e.value)
 
 
 def test_null_arguments(lib):
