@@ -25,12 +25,15 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_frame_kernel_plain-640x480.json")
 
 
+# the sources the per-frame kernel is compiled from
+FRAME_KERNEL_SOURCES = ("gmm_device.hpp", "gmm_frame.hpp", "gmm_internal.hpp", "gmm_kernels.hip")
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2110_14934_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in FRAME_KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -79,6 +82,116 @@ def cpu_baseline(wl, seconds: float):
             "host_cpus": os.cpu_count()}
 
 
+def stream_bytes(spec, holes: float, M: int, esize: int, fused: bool) -> float:
+    """Algorithmic bytes of one stream in one batched launch (see bytes_per_frame)."""
+    n = spec.npix
+    b = 0.0
+    if spec.rgb:
+        b += n * (2 * 5 * M * esize + 3 + 1 / 8)
+    if spec.depth:
+        b += n * (2 + 1 / 8) + (n - holes) * (2 * 3 * M * esize)
+    if fused:
+        b += n * (2 + 1 / 8)
+    return b
+
+
+def bench_batch(args) -> int:
+    """Many streams, one persistent launch per frame-set, replayed from a captured hipGraph."""
+    import torch
+    from paper_2110_14934_amd import _abi, Segmenter, Batch, GMM_RGB, GMM_DEPTH
+    from paper_2110_14934_amd.synth import Stream, workload
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2110_14934_amd.build import build
+        build()
+    dev = torch.device("cuda", 0)
+    wl = workload(args.workload)
+    dtype = args.state_dtype or wl.state_dtype
+    esize = 4 if dtype == "f32" else 2
+    M = wl.mix.M
+    F = args.clip or (wl.frames if args.workload == "batch-64" else 24)
+    streams = [Stream(sp) for sp in wl.streams]
+    frames, holes = [], []
+    for t in range(F):
+        fs, hs = [], []
+        for st in streams:
+            rgb = st.rgb(t, device=dev) if st.spec.rgb else None
+            dep = st.depth(t, device=dev) if st.spec.depth else None
+            fs.append((rgb, dep))
+            hs.append((dep == 0).sum() if dep is not None else torch.zeros((), device=dev, dtype=torch.int64))
+        frames.append(fs)
+        holes.append(torch.stack(hs))
+        if t % 20 == 19:
+            print(f"[bench] generated {t + 1}/{F} frame-sets", file=sys.stderr, flush=True)
+    holes = torch.stack(holes).to(torch.float64).cpu().numpy()   # (F, streams)
+    torch.cuda.synchronize()
+    print(f"[bench] {len(streams)} streams x {F} frame-sets resident", file=sys.stderr, flush=True)
+
+    segs = []
+    for sp in wl.streams:
+        mods = (GMM_RGB if sp.rgb else 0) | (GMM_DEPTH if sp.depth else 0)
+        segs.append(Segmenter(sp.width, sp.height, mods, M, state_dtype=dtype))
+    batch = Batch(segs, n_slots=F)
+    stream = torch.cuda.Stream()
+    for t in range(F):
+        batch.set_frames(t, frames[t], stream=stream)
+    stream.synchronize()
+    tune_ms = None
+    if not args.no_autotune:
+        best, tune_ms = batch.autotune(0, stream)
+        print(f"[bench] autotuned {best}: {tune_ms:.3f} ms per launch", file=sys.stderr, flush=True)
+    K, W = args.steps, args.warmup
+    if K % F:
+        K = max(F, (K // F) * F)
+    with torch.cuda.stream(stream):
+        for i in range(W):
+            batch.run(i % F, stream)
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for i in range(F):
+            batch.run((W + i) % F, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        for _ in range(K // F):
+            graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / K
+    pu_step = sum(sp.npix * (int(sp.rgb) + int(sp.depth)) for sp in wl.streams)
+    value = pu_step * K / (ms_total / 1e3)
+    mean_holes = holes[[(W + i) % F for i in range(K)]].mean(axis=0)
+    alg = sum(stream_bytes(sp, float(mean_holes[i]), M, esize, sp.rgb and sp.depth)
+              for i, sp in enumerate(wl.streams))
+    achieved = alg / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": "RGBD GMM pixel-updates/s", "value": value, "unit": "pixel-updates/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Kinect-shaped RGB-D streams; the paper's captures are not available)",
+        "config": {"workload": args.workload, "streams": len(wl.streams), "M": M, "state_dtype": dtype,
+                   "clip_frames": F, "launch": "graph", "tuning": list(batch.tuning()),
+                   "autotune_ms": tune_ms},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"rgbd::batch_kernel<{M}, {dtype}, {batch.tuning()[0]}>",
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": ms_step * 1e3},
+        "state_bytes": sum(sg.state_bytes() for sg in segs),
+    }
+    batch.close()
+    for sg in segs:
+        sg.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +200,11 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="plain-640x480")
     ap.add_argument("--mode", choices=("graph", "eager"), default="graph",
                     help="graph: replay a captured hipGraph of the whole clip; eager: one launch per call")
+    ap.add_argument("--state-dtype", choices=("f32", "f16", "bf16"), default=None,
+                    help="override the workload's mixture-state storage type (batched workloads)")
+    ap.add_argument("--clip", type=int, default=0,
+                    help="batched workloads: distinct frame-sets generated and cycled (default: all)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--host-frames", type=int, default=0, metavar="N",
@@ -100,8 +218,10 @@ def main(argv=None) -> int:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         return 2
+    if args.workload in ("batch-64", "precision-256"):
+        return bench_batch(args)
     if args.workload != "plain-640x480":
-        print("only the plain-640x480 workload is benchmarked by this script", file=sys.stderr)
+        print("workloads: plain-640x480 (default), batch-64, precision-256", file=sys.stderr)
         return 2
 
     import torch

@@ -161,6 +161,80 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream);
  */
 gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream);
 
+/* ---- batched path: many streams, one persistent launch per frame-set --------------------- */
+
+typedef struct gmm_batch gmm_batch;
+
+/* One stream's frame and masks in a batched call; the same rules as gmm_apply_frame (device
+ * pointers, pitches, NULL for an absent modality). `fused` is optional: non-NULL (two-modality
+ * streams only) runs List 1 for that stream in the same launch, like gmm_apply_frame_fused. */
+typedef struct {
+  const uint8_t* rgb;
+  int64_t rgb_pitch_bytes;
+  const uint16_t* depth;
+  int64_t depth_pitch_bytes;
+  uint64_t* fg_rgb;
+  uint64_t* fg_depth;
+  uint64_t* fused;
+} gmm_stream_io;
+
+/* Launch shape of the persistent kernel: threads per block (256 or 512), pixels per tile (a
+ * multiple of block_threads, at most 64x it; a tile never spans two streams) and resident
+ * blocks per compute unit (1..32; grid = blocks_per_cu x CU count, capped at the tile count). */
+typedef struct {
+  int32_t block_threads;
+  int32_t tile_pixels;
+  int32_t blocks_per_cu;
+} gmm_batch_tuning;
+
+/*
+ * Group existing handles (same device, same M, same state dtype; each at most once) so that one
+ * launch advances all of them by one frame. Uneven resolutions and modality mixes are allowed.
+ * `n_slots` descriptor slots (1..4096) hold prepared frame-sets, so launches can be captured in
+ * a hipGraph and replayed. The handles must outlive the batch and must not be used by other
+ * calls while batch work on them is in flight. Default tuning: {256, 1024, 8}.
+ */
+gmm_status gmm_batch_create(gmm_handle* const* handles, int32_t n, int32_t n_slots, gmm_batch** out);
+
+/* Release a batch (synchronises its last stream first); the handles stay valid. NULL: no-op. */
+gmm_status gmm_batch_destroy(gmm_batch* b);
+
+/* Set / query the launch shape. Setting it synchronises the batch's last stream and invalidates
+ * graphs captured with the previous shape. */
+gmm_status gmm_batch_set_tuning(gmm_batch* b, const gmm_batch_tuning* t);
+gmm_status gmm_batch_get_tuning(const gmm_batch* b, gmm_batch_tuning* t);
+
+/*
+ * Prepare descriptor slot `slot` with one gmm_stream_io per handle (host array, in the order of
+ * gmm_batch_create). Every stream is validated first; on error nothing changes. The descriptors
+ * are uploaded asynchronously on `stream`; the host array may be reused when the call returns.
+ */
+gmm_status gmm_batch_set_frames(gmm_batch* b, int32_t slot, const gmm_stream_io* io, void* stream);
+
+/*
+ * Advance every stream of the batch one frame using the frames and masks of slot `slot`, in one
+ * persistent launch on `stream`. Per stream, results (masks and state) are bit-identical to
+ * gmm_apply_frame (or gmm_apply_frame_fused when `fused` was given). Allocates nothing and does
+ * not synchronise: safe to capture in a hipGraph.
+ */
+gmm_status gmm_batch_run(gmm_batch* b, int32_t slot, void* stream);
+
+/* gmm_batch_set_frames(b, 0, io, stream) followed by gmm_batch_run(b, 0, stream). */
+gmm_status gmm_batch_apply(gmm_batch* b, const gmm_stream_io* io, void* stream);
+
+/*
+ * Choose the launch shape by timing trial launches of slot `slot` over block_threads {256, 512}
+ * x tile multiples {1, 2, 4, 8, 16} x blocks_per_cu {2, 4, 8, 16}, keep the fastest, and cache
+ * it for this process per (device, M, state dtype, multiset of stream shapes and modalities).
+ * Every stream's state is saved first and restored afterwards (the slot's masks are
+ * overwritten by the trials). Synchronous. Reports the winner and its time per launch.
+ */
+gmm_status gmm_batch_autotune(gmm_batch* b, int32_t slot, void* stream, gmm_batch_tuning* best,
+                              double* best_ms);
+
+/* Number of tiles of one launch under the current tuning. */
+gmm_status gmm_batch_tiles(const gmm_batch* b, uint32_t* n_tiles);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t gmm_version(void);
 

@@ -12,7 +12,9 @@ from . import _abi
 from ._abi import (GMM_RGB, GMM_DEPTH, GMM_F32, GMM_F16, GMM_BF16, GMM_HOLE_SKIP, GMM_HOLE_AS_VALUE,
                    GmmError, gmm_config, gmm_config_default, gmm_create, gmm_destroy, gmm_apply_frame,
                    gmm_fuse, gmm_apply_frame_fused, gmm_last_error, gmm_state_bytes, gmm_state_size,
-                   gmm_read_state, gmm_write_state, gmm_version)
+                   gmm_read_state, gmm_write_state, gmm_version, stream_io, gmm_batch_create,
+                   gmm_batch_destroy, gmm_batch_set_tuning, gmm_batch_get_tuning, gmm_batch_set_frames,
+                   gmm_batch_run, gmm_batch_apply, gmm_batch_autotune, gmm_batch_tiles)
 
 
 def mask_words(npix: int) -> int:
@@ -70,6 +72,50 @@ class Segmenter:
     def close(self):
         if self.handle is not None:
             gmm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A set of Segmenters advanced together by one persistent launch per frame-set."""
+
+    def __init__(self, segmenters, n_slots: int = 1):
+        self.segs = list(segmenters)
+        self.handle = gmm_batch_create([s.handle for s in self.segs], n_slots)
+
+    def ios(self, frames, fuse=True):
+        """frames: list of (rgb or None, depth or None) per stream, in batch order."""
+        out = []
+        for seg, (rgb, depth) in zip(self.segs, frames):
+            out.append(stream_io(rgb, depth, seg.fg_rgb, seg.fg_depth, seg.fused if fuse else None))
+        return out
+
+    def set_frames(self, slot, frames, fuse=True, stream=None):
+        gmm_batch_set_frames(self.handle, slot, self.ios(frames, fuse), stream)
+
+    def run(self, slot=0, stream=None):
+        gmm_batch_run(self.handle, slot, stream)
+
+    def apply(self, frames, fuse=True, stream=None):
+        gmm_batch_apply(self.handle, self.ios(frames, fuse), stream)
+
+    def set_tuning(self, block_threads, tile_pixels, blocks_per_cu):
+        gmm_batch_set_tuning(self.handle, block_threads, tile_pixels, blocks_per_cu)
+
+    def tuning(self):
+        return gmm_batch_get_tuning(self.handle)
+
+    def autotune(self, slot=0, stream=None):
+        return gmm_batch_autotune(self.handle, slot, stream)
+
+    def close(self):
+        if self.handle is not None:
+            gmm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -33,6 +33,8 @@ EXPORTS = (
     "gmm_config_default", "gmm_create", "gmm_destroy", "gmm_apply_frame", "gmm_fuse",
     "gmm_apply_frame_fused", "gmm_last_error", "gmm_state_bytes", "gmm_state_size",
     "gmm_read_state", "gmm_write_state", "gmm_version",
+    "gmm_batch_create", "gmm_batch_destroy", "gmm_batch_set_tuning", "gmm_batch_get_tuning",
+    "gmm_batch_set_frames", "gmm_batch_run", "gmm_batch_apply", "gmm_batch_autotune", "gmm_batch_tiles",
 )
 
 
@@ -51,6 +53,22 @@ class gmm_config(ctypes.Structure):
         ("w_init", ctypes.c_float),
         ("hole_policy", ctypes.c_int32), ("state_dtype", ctypes.c_int32), ("device", ctypes.c_int32),
     ]
+
+
+class gmm_stream_io(ctypes.Structure):
+    _fields_ = [
+        ("rgb", ctypes.c_void_p), ("rgb_pitch_bytes", ctypes.c_int64),
+        ("depth", ctypes.c_void_p), ("depth_pitch_bytes", ctypes.c_int64),
+        ("fg_rgb", ctypes.c_void_p), ("fg_depth", ctypes.c_void_p), ("fused", ctypes.c_void_p),
+    ]
+
+
+class gmm_batch_tuning(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("tile_pixels", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.block_threads, self.tile_pixels, self.blocks_per_cu)
 
 
 _lib = None
@@ -81,6 +99,16 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "gmm_read_state": (st, [H, vp, vp]),
         "gmm_write_state": (st, [H, vp, vp]),
         "gmm_version": (ctypes.c_int32, []),
+        "gmm_batch_create": (st, [ctypes.POINTER(H), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(H)]),
+        "gmm_batch_destroy": (st, [H]),
+        "gmm_batch_set_tuning": (st, [H, ctypes.POINTER(gmm_batch_tuning)]),
+        "gmm_batch_get_tuning": (st, [H, ctypes.POINTER(gmm_batch_tuning)]),
+        "gmm_batch_set_frames": (st, [H, ctypes.c_int32, ctypes.POINTER(gmm_stream_io), vp]),
+        "gmm_batch_run": (st, [H, ctypes.c_int32, vp]),
+        "gmm_batch_apply": (st, [H, ctypes.POINTER(gmm_stream_io), vp]),
+        "gmm_batch_autotune": (st, [H, ctypes.c_int32, vp, ctypes.POINTER(gmm_batch_tuning),
+                                    ctypes.POINTER(ctypes.c_double)]),
+        "gmm_batch_tiles": (st, [H, ctypes.POINTER(ctypes.c_uint32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -181,3 +209,70 @@ def gmm_write_state(h, state, stream=None):
 
 def gmm_version() -> int:
     return load().gmm_version()
+
+
+# ---- batched path ------------------------------------------------------------------------
+
+def stream_io(rgb=None, depth=None, fg_rgb=None, fg_depth=None, fused=None) -> gmm_stream_io:
+    """One stream's entry of a batched call; pitches are taken from the tensors' row strides."""
+    io = gmm_stream_io()
+    io.rgb = _ptr(rgb)
+    io.rgb_pitch_bytes = rgb.stride(0) * rgb.element_size() if rgb is not None else 0
+    io.depth = _ptr(depth)
+    io.depth_pitch_bytes = depth.stride(0) * depth.element_size() if depth is not None else 0
+    io.fg_rgb = _ptr(fg_rgb)
+    io.fg_depth = _ptr(fg_depth)
+    io.fused = _ptr(fused)
+    return io
+
+
+def gmm_batch_create(handles, n_slots: int = 1) -> int:
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    b = ctypes.c_void_p()
+    _check(load().gmm_batch_create(arr, len(handles), n_slots, ctypes.byref(b)))
+    return b.value
+
+
+def gmm_batch_destroy(b):
+    _check(load().gmm_batch_destroy(b))
+
+
+def gmm_batch_set_tuning(b, block_threads: int, tile_pixels: int, blocks_per_cu: int):
+    t = gmm_batch_tuning(block_threads, tile_pixels, blocks_per_cu)
+    _check(load().gmm_batch_set_tuning(b, ctypes.byref(t)))
+
+
+def gmm_batch_get_tuning(b):
+    t = gmm_batch_tuning()
+    _check(load().gmm_batch_get_tuning(b, ctypes.byref(t)))
+    return t.as_tuple()
+
+
+def _io_array(ios):
+    return (gmm_stream_io * len(ios))(*ios)
+
+
+def gmm_batch_set_frames(b, slot: int, ios, stream=None):
+    _check(load().gmm_batch_set_frames(b, slot, _io_array(ios), _stream(stream)))
+
+
+def gmm_batch_run(b, slot: int = 0, stream=None):
+    _check(load().gmm_batch_run(b, slot, _stream(stream)))
+
+
+def gmm_batch_apply(b, ios, stream=None):
+    _check(load().gmm_batch_apply(b, _io_array(ios), _stream(stream)))
+
+
+def gmm_batch_autotune(b, slot: int = 0, stream=None):
+    """Returns ((block_threads, tile_pixels, blocks_per_cu), ms per launch)."""
+    t = gmm_batch_tuning()
+    ms = ctypes.c_double()
+    _check(load().gmm_batch_autotune(b, slot, _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
+    return t.as_tuple(), ms.value
+
+
+def gmm_batch_tiles(b) -> int:
+    n = ctypes.c_uint32()
+    _check(load().gmm_batch_tiles(b, ctypes.byref(n)))
+    return n.value

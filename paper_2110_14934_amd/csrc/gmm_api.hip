@@ -17,33 +17,14 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-static gmm_status fail(gmm_status st, const std::string& msg) {
+gmm_status fail(gmm_status st, const std::string& msg) {
   set_error(msg);
   return st;
 }
 
-static gmm_status hip_fail(hipError_t e, const char* what) {
+gmm_status hip_fail(hipError_t e, const char* what) {
   return fail(GMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-// Switches to the handle's device for the duration of a call, restoring the caller's.
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) {
-    ok_ = hipGetDevice(&prev_) == hipSuccess;
-    if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
-    switched_ = ok_ && prev_ != dev;
-  }
-  ~DeviceGuard() {
-    if (switched_) (void)hipSetDevice(prev_);
-  }
-  bool ok() const { return ok_; }
-
- private:
-  int prev_ = 0;
-  bool ok_ = false;
-  bool switched_ = false;
-};
 
 static inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -121,25 +102,6 @@ static void unpack_values(const void* in, double* out, size_t n, int dtype) {
 
 using namespace rgbd;
 
-struct gmm_handle {
-  gmm_config cfg;
-  int64_t npix = 0;
-  int64_t stride = 0;       // elements per plane
-  size_t esize = 0;         // bytes per stored value
-  size_t rgb_bytes = 0;     // colour block
-  size_t depth_bytes = 0;   // depth block
-  size_t fuse_bytes = 0;    // List 1 state bytes (padded)
-  void* mem = nullptr;      // one device allocation: [colour][depth][fusion]
-  void* st_rgb = nullptr;
-  void* st_depth = nullptr;
-  uint8_t* fstate = nullptr;
-  hipStream_t last_stream = nullptr;
-  ModelConsts kc{}, kd{};
-};
-
-static bool has_rgb(const gmm_handle* h) { return (h->cfg.modalities & GMM_RGB) != 0; }
-static bool has_depth(const gmm_handle* h) { return (h->cfg.modalities & GMM_DEPTH) != 0; }
-static bool has_both(const gmm_handle* h) { return has_rgb(h) && has_depth(h); }
 
 static gmm_status validate_config(const gmm_config* c) {
   if (!c) return fail(GMM_ERR_INVALID_ARG, "config is NULL");
@@ -296,7 +258,7 @@ gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles) {
 
 }  // extern "C"
 
-static gmm_status check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
+gmm_status rgbd::check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
                                    const uint16_t* depth, int64_t depth_pitch, uint64_t* fg_rgb,
                                    uint64_t* fg_depth) {
   if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
@@ -321,7 +283,7 @@ static gmm_status check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rg
   return GMM_OK;
 }
 
-static FrameArgs frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
+FrameArgs rgbd::frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
                             const uint16_t* depth, int64_t depth_pitch, uint64_t* fg_rgb,
                             uint64_t* fg_depth, uint64_t* fused) {
   FrameArgs a{};
@@ -343,6 +305,7 @@ static FrameArgs frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch
   a.fused = fused;
   a.kc = h->kc;
   a.kd = h->kd;
+  a.mode = (has_rgb(h) ? kModeRGB : 0) | (has_depth(h) ? kModeDepth : 0) | (fused ? kModeFuse : 0);
   return a;
 }
 

@@ -30,6 +30,8 @@ struct FrameArgs {
   uint64_t* fused;
   ModelConsts kc;          // colour constants
   ModelConsts kd;          // depth constants
+  int32_t mode;            // kModeRGB | kModeDepth | kModeFuse bits of this stream
+  int32_t pad_;
 };
 
 enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4 };
@@ -46,5 +48,54 @@ bool frame_variant_compiled(int M, int dtype);
 inline size_t dtype_size(int dtype) { return dtype == GMM_F32 ? 4 : 2; }
 
 void set_error(const std::string& msg);
+gmm_status fail(gmm_status st, const std::string& msg);
+gmm_status hip_fail(hipError_t e, const char* what);
 
+// Switches to a device for the duration of a call, restoring the caller's.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    ok_ = hipGetDevice(&prev_) == hipSuccess;
+    if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    switched_ = ok_ && prev_ != dev;
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = 0;
+  bool ok_ = false;
+  bool switched_ = false;
+};
+
+}  // namespace rgbd
+
+struct gmm_handle {  // the library's per-stream object (opaque in gmm.h)
+  gmm_config cfg;
+  int64_t npix = 0;
+  int64_t stride = 0;       // elements per plane
+  size_t esize = 0;         // bytes per stored value
+  size_t rgb_bytes = 0;     // colour block
+  size_t depth_bytes = 0;   // depth block
+  size_t fuse_bytes = 0;    // List 1 state bytes (padded)
+  void* mem = nullptr;      // one device allocation: [colour][depth][fusion]
+  void* st_rgb = nullptr;
+  void* st_depth = nullptr;
+  uint8_t* fstate = nullptr;
+  hipStream_t last_stream = nullptr;
+  rgbd::ModelConsts kc{}, kd{};
+};
+
+inline bool has_rgb(const gmm_handle* h) { return (h->cfg.modalities & GMM_RGB) != 0; }
+inline bool has_depth(const gmm_handle* h) { return (h->cfg.modalities & GMM_DEPTH) != 0; }
+inline bool has_both(const gmm_handle* h) { return has_rgb(h) && has_depth(h); }
+
+namespace rgbd {
+// Validation and kernel arguments of one stream's frame (shared by the plain and batched paths).
+gmm_status check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch, const uint16_t* depth,
+                            int64_t depth_pitch, uint64_t* fg_rgb, uint64_t* fg_depth);
+FrameArgs frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch, const uint16_t* depth,
+                     int64_t depth_pitch, uint64_t* fg_rgb, uint64_t* fg_depth, uint64_t* fused);
 }  // namespace rgbd

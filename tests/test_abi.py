@@ -95,6 +95,30 @@ def test_null_arguments(lib):
     assert lib.gmm_config_default(None, 1, 1, 1, 1) == _abi.GMM_ERR_INVALID_ARG
 
 
+def test_batch_null_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.gmm_batch_create(None, 0, 1, ctypes.byref(out)) == _abi.GMM_ERR_INVALID_ARG
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.gmm_batch_create(arr, 2, 1, ctypes.byref(out)) == _abi.GMM_ERR_INVALID_ARG
+    assert "NULL handle" in _abi.gmm_last_error()
+    assert lib.gmm_batch_create(arr, 2, 0, ctypes.byref(out)) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_batch_destroy(None) == _abi.GMM_OK
+    assert lib.gmm_batch_run(None, 0, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_batch_set_frames(None, 0, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_batch_apply(None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_batch_autotune(None, 0, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    t = _abi.gmm_batch_tuning()
+    assert lib.gmm_batch_set_tuning(None, ctypes.byref(t)) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_batch_get_tuning(None, ctypes.byref(t)) == _abi.GMM_ERR_INVALID_ARG
+    n = ctypes.c_uint32()
+    assert lib.gmm_batch_tiles(None, ctypes.byref(n)) == _abi.GMM_ERR_INVALID_ARG
+
+
+def test_batch_struct_layouts(lib):
+    assert ctypes.sizeof(_abi.gmm_stream_io) == 7 * 8
+    assert ctypes.sizeof(_abi.gmm_batch_tuning) == 3 * 4
+
+
 def test_config_struct_layout_matches_header(lib):
     # 4 ints, 3 floats, 2x2 floats, 1 float, 3 ints = 15 four-byte fields
     assert ctypes.sizeof(_abi.gmm_config) == 15 * 4

@@ -1,0 +1,273 @@
+"""The batched persistent launch: bit-identical to one launch per stream, autotuning that
+leaves the streams untouched, hipGraph capture and replay, and the full-size batch workload
+against the FP64 oracle on sampled pixels."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import MixParams, MixtureOracle, FusionOracle
+from paper_2110_14934_amd import (GMM_RGB, GMM_DEPTH, Batch, GmmError, Segmenter, _abi, gmm_batch_create)
+from paper_2110_14934_amd.synth import Stream, StreamSpec, workload, MixtureSettings
+from tests.parity import unpack_mask, from_canonical, excused, param_mismatch, oracle_state, \
+    WEIGHT_MARGIN_FREE, KEY_GAP_FREE
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mods(spec):
+    return (GMM_RGB if spec.rgb else 0) | (GMM_DEPTH if spec.depth else 0)
+
+
+def kwargs(mix):
+    return dict(alpha=mix.alpha, k=mix.k, T=mix.T, sigma0=(mix.sigma0_rgb, mix.sigma0_depth),
+                var_min=(mix.var_min_rgb, mix.var_min_depth), w_init=mix.w_init)
+
+
+SPECS = [
+    StreamSpec(160, 120, n_boxes=1, box_min=20, box_max=20, hole_p=0.02, seed=11, index=0),
+    StreamSpec(97, 33, n_boxes=2, box_min=5, box_max=10, hole_p=0.05, seed=11, index=1),
+    StreamSpec(64, 48, rgb=False, depth=True, n_boxes=1, box_min=8, box_max=12, hole_p=0.05, seed=11, index=2),
+    StreamSpec(200, 100, rgb=True, depth=False, n_boxes=2, box_min=10, box_max=30, seed=11, index=3),
+    StreamSpec(17, 13, n_boxes=1, box_min=3, box_max=5, hole_p=0.1, seed=11, index=4),
+]
+MIX = MixtureSettings(M=5, alpha=0.05, w_init=0.05)
+
+
+def _frames(streams, t):
+    out = []
+    for st in streams:
+        rgb = st.rgb(t, device=DEV) if st.spec.rgb else None
+        dep = st.depth(t, device=DEV) if st.spec.depth else None
+        out.append((rgb, dep))
+    return out
+
+
+def _single_step(seg, rgb, dep):
+    if rgb is not None and dep is not None:
+        seg.apply_fused(rgb, dep)
+    else:
+        seg.apply(rgb, dep)
+
+
+def _compare_bitwise(a_segs, b_segs, t):
+    for i, (a, b) in enumerate(zip(a_segs, b_segs)):
+        for x, y in ((a.fg_rgb, b.fg_rgb), (a.fg_depth, b.fg_depth), (a.fused, b.fused)):
+            if x is not None:
+                assert torch.equal(x, y), (t, i)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_batch_bit_identical_to_single_streams(dtype):
+    streams = [Stream(s) for s in SPECS]
+    single = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, **kwargs(MIX)) for s in SPECS]
+    batched = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, **kwargs(MIX)) for s in SPECS]
+    batch = Batch(batched)
+    tunings = [(256, 256, 1), (512, 2048, 4), (256, 4096, 16), (512, 512, 2)]
+    try:
+        for t in range(16):
+            frames = _frames(streams, t)
+            for seg, (rgb, dep) in zip(single, frames):
+                _single_step(seg, rgb, dep)
+            batch.set_tuning(*tunings[t % len(tunings)])
+            batch.apply(frames)
+            torch.cuda.synchronize()
+            _compare_bitwise(single, batched, t)
+        for a, b in zip(single, batched):
+            assert np.array_equal(a.read_state(), b.read_state())
+    finally:
+        batch.close()
+        for s in single + batched:
+            s.close()
+
+
+def test_autotune_leaves_state_untouched_and_picks_a_candidate():
+    streams = [Stream(s) for s in SPECS]
+    segs = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
+    ref = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
+    batch = Batch(segs)
+    try:
+        for t in range(3):
+            frames = _frames(streams, t)
+            batch.apply(frames)
+            for seg, (rgb, dep) in zip(ref, frames):
+                _single_step(seg, rgb, dep)
+        torch.cuda.synchronize()
+        before = [s.read_state() for s in segs]
+        batch.set_frames(0, _frames(streams, 3))
+        best, ms = batch.autotune(0)
+        assert best[0] in (256, 512) and best[1] % best[0] == 0 and best[2] in (2, 4, 8, 16)
+        assert ms > 0
+        assert batch.tuning() == best
+        after = [s.read_state() for s in segs]
+        for x, y in zip(before, after):
+            assert np.array_equal(x, y)
+        # a second call hits the per-process cache and returns the same choice
+        best2, ms2 = batch.autotune(0)
+        assert best2 == best and ms2 == ms
+        # the batch continues exactly like the single-stream path
+        for t in range(3, 8):
+            frames = _frames(streams, t)
+            batch.apply(frames)
+            for seg, (rgb, dep) in zip(ref, frames):
+                _single_step(seg, rgb, dep)
+            torch.cuda.synchronize()
+            _compare_bitwise(ref, segs, t)
+    finally:
+        batch.close()
+        for s in segs + ref:
+            s.close()
+
+
+def test_batch_graph_replay_matches_eager():
+    streams = [Stream(s) for s in SPECS]
+    S = 4
+    frames = [_frames(streams, t) for t in range(S)]
+    g_segs = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
+    e_segs = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
+    gb = Batch(g_segs, n_slots=S)
+    eb = Batch(e_segs, n_slots=S)
+    cap = torch.cuda.Stream()
+    try:
+        for slot in range(S):
+            gb.set_frames(slot, frames[slot], stream=cap)
+            eb.set_frames(slot, frames[slot])
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=cap):
+            for slot in range(S):
+                gb.run(slot, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        for rep in range(3):
+            graph.replay()
+            torch.cuda.synchronize()
+            scratch = torch.randn(1 << 20, device=DEV).sum()   # unrelated eager work in between
+            for slot in range(S):
+                eb.run(slot)
+                if slot == S - 1:
+                    torch.cuda.synchronize()
+            _compare_bitwise(e_segs, g_segs, rep)
+            for a, b in zip(e_segs, g_segs):
+                assert np.array_equal(a.read_state(), b.read_state()), rep
+            del scratch
+    finally:
+        gb.close()
+        eb.close()
+        for s in g_segs + e_segs:
+            s.close()
+
+
+def test_batch_error_paths():
+    a = Segmenter(32, 8, GMM_RGB | GMM_DEPTH, 3)
+    b = Segmenter(32, 8, GMM_RGB | GMM_DEPTH, 4)
+    c = Segmenter(16, 8, GMM_RGB, 3)
+    try:
+        with pytest.raises(GmmError) as e:
+            gmm_batch_create([a.handle, b.handle])
+        assert e.value.status == _abi.GMM_ERR_INVALID_ARG
+        with pytest.raises(GmmError):
+            gmm_batch_create([a.handle, a.handle])
+        bt = Batch([a, c], n_slots=2)
+        with pytest.raises(GmmError) as e:
+            bt.run(1)
+        assert e.value.status == _abi.GMM_ERR_STATE
+        with pytest.raises(GmmError) as e:
+            bt.run(2)
+        assert e.value.status == _abi.GMM_ERR_INVALID_ARG
+        rgb = torch.zeros(8, 32, 3, dtype=torch.uint8, device=DEV)
+        dep = torch.zeros(8, 32, dtype=torch.uint16, device=DEV)
+        rgb_c = torch.zeros(8, 16, 3, dtype=torch.uint8, device=DEV)
+        ios = [_abi.stream_io(rgb, dep, a.fg_rgb, a.fg_depth, a.fused),
+               _abi.stream_io(rgb_c, None, c.fg_rgb, None, c.fg_rgb)]   # fusion on a colour-only stream
+        with pytest.raises(GmmError) as e:
+            _abi.gmm_batch_set_frames(bt.handle, 0, ios)
+        assert e.value.status == _abi.GMM_ERR_STATE
+        with pytest.raises(GmmError):
+            bt.set_tuning(384, 768, 2)
+        with pytest.raises(GmmError):
+            bt.set_tuning(256, 300, 2)
+        bt.set_frames(0, [(rgb, dep), (rgb_c, None)])
+        bt.run(0)
+        torch.cuda.synchronize()
+        bt.close()
+    finally:
+        for s in (a, b, c):
+            s.close()
+
+
+def _mix_params(mix, modality):
+    if modality == "rgb":
+        return MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_rgb, mix.var_min_rgb, mix.w_init)
+    return MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_depth, mix.var_min_depth, mix.w_init,
+                     hole_skip=mix.hole_skip)
+
+
+def test_full_size_batch_workload_sampled_pixels():
+    """The 64-stream mix (16x320x240 + 32x640x480 RGB-D, 8x512x424 depth, 8x1920x1080 colour)
+    at full size, autotuned, 24 frames of the persistent launch; the oracle follows 1024 sampled
+    pixels of one stream of each kind."""
+    wl = workload("batch-64")
+    mix = wl.mix
+    streams = [Stream(s) for s in wl.streams]
+    segs = [Segmenter(s.width, s.height, mods(s), mix.M) for s in wl.streams]
+    batch = Batch(segs)
+    picks = [0, 16, 48, 56]   # 320x240 RGB-D, 640x480 RGB-D, 512x424 depth, 1920x1080 colour
+    rng = np.random.default_rng(3)
+    follow = {}
+    for i in picks:
+        sp = wl.streams[i]
+        pix = np.unique(np.concatenate([rng.choice(sp.npix, 1024, replace=False), np.arange(sp.npix - 100, sp.npix)]))
+        k = pix.size
+        col = MixtureOracle(_mix_params(mix, "rgb"), 3, k) if sp.rgb else None
+        dep = MixtureOracle(_mix_params(mix, "depth"), 1, k) if sp.depth else None
+        fus = FusionOracle(k) if (sp.rgb and sp.depth) else None
+        follow[i] = (pix, col, dep, fus, np.zeros(k, bool), np.zeros(k, bool))
+    say(f"batch-64 full size: {sum(s.npix for s in wl.streams)} pixels, {len(segs)} streams")
+    try:
+        for t in range(24):
+            frames = _frames(streams, t)
+            if t == 0:
+                batch.set_frames(0, frames)
+                say("  autotune", batch.autotune(0))
+            batch.apply(frames)
+            torch.cuda.synchronize()
+            for i, (pix, col, dep, fus, rc, rd) in follow.items():
+                st = streams[i]
+                tp = torch.from_numpy(pix)
+                seg = segs[i]
+                n = st.spec.npix
+                ic = col.step(st.rgb(t, pix=tp).numpy()) if col is not None else None
+                idd = dep.step(st.depth(t, pix=tp).numpy()) if dep is not None else None
+                if ic is not None:
+                    rc |= excused(ic, WEIGHT_MARGIN_FREE, KEY_GAP_FREE)
+                    g = unpack_mask(seg.fg_rgb, n)[pix]
+                    assert not np.any((g != ic.fg) & ~rc), (i, t)
+                if idd is not None:
+                    rd |= excused(idd, WEIGHT_MARGIN_FREE, KEY_GAP_FREE)
+                    g = unpack_mask(seg.fg_depth, n)[pix]
+                    assert not np.any((g != idd.fg) & ~rd), (i, t)
+                if fus is not None:
+                    fo = fus.step(ic.fg, idd.fg)
+                    g = unpack_mask(seg.fused, n)[pix]
+                    assert not np.any((g != fo) & ~(rc | rd)), (i, t)
+        for i, (pix, col, dep, fus, rc, rd) in follow.items():
+            sp = wl.streams[i]
+            got = from_canonical(segs[i].read_state(), mix.M, sp.npix, sp.rgb, sp.depth)
+            if col is not None:
+                g = tuple(a[..., pix] for a in got["rgb"])
+                assert not np.any(param_mismatch(g, oracle_state(col)) & ~rc), i
+            if dep is not None:
+                g = tuple(a[..., pix] for a in got["depth"])
+                assert not np.any(param_mismatch(g, oracle_state(dep)) & ~rd), i
+        say("  sampled pixels match the oracle")
+    finally:
+        batch.close()
+        for s in segs:
+            s.close()
