@@ -185,9 +185,9 @@ gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
   if (!h) return fail(GMM_ERR_OUT_OF_MEMORY, "host allocation of the handle failed");
   h->cfg = *cfg;
   h->npix = static_cast<int64_t>(cfg->width) * cfg->height;
-  h->stride = round_up(h->npix, 128);
+  h->tiles64 = static_cast<uint32_t>((h->npix + kWave - 1) / kWave);
   h->esize = dtype_size(cfg->state_dtype);
-  const size_t plane = static_cast<size_t>(h->stride) * h->esize;
+  const size_t plane = static_cast<size_t>(h->tiles64) * kWave * h->esize;  // one plane, all tiles
   h->rgb_bytes = has_rgb(h) ? plane * 5 * cfg->M : 0;
   h->depth_bytes = has_depth(h) ? plane * 3 * cfg->M : 0;
   h->fuse_bytes = has_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
@@ -215,9 +215,9 @@ gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
   h->fstate = has_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
 
   e = hipSuccess;
-  if (has_rgb(h)) e = launch_init(h->st_rgb, cfg->state_dtype, h->stride, cfg->M, 3, h->kc.var0, nullptr);
+  if (has_rgb(h)) e = launch_init(h->st_rgb, cfg->state_dtype, h->tiles64, cfg->M, 3, h->kc.var0, nullptr);
   if (e == hipSuccess && has_depth(h))
-    e = launch_init(h->st_depth, cfg->state_dtype, h->stride, cfg->M, 1, h->kd.var0, nullptr);
+    e = launch_init(h->st_depth, cfg->state_dtype, h->tiles64, cfg->M, 1, h->kd.var0, nullptr);
   if (e == hipSuccess && has_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
@@ -288,7 +288,7 @@ FrameArgs rgbd::frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
                             uint64_t* fg_depth, uint64_t* fused) {
   FrameArgs a{};
   a.npix = h->npix;
-  a.stride = h->stride;
+  a.tiles64 = h->tiles64;
   a.width = h->cfg.width;
   a.rgb = rgb;
   a.rgb_pitch = rgb_pitch;
@@ -380,18 +380,23 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "state copy to host");
   const size_t n = static_cast<size_t>(h->npix), M = static_cast<size_t>(h->cfg.M);
-  const size_t plane = static_cast<size_t>(h->stride) * h->esize;
   double* o = host_out;
   size_t off = 0;
   for (int blk = 0; blk < 2; ++blk) {
     const bool present = blk == 0 ? has_rgb(h) : has_depth(h);
     if (!present) continue;
-    const int P = blk == 0 ? 5 : 3;
-    for (size_t pl = 0; pl < P * M; ++pl) {
-      unpack_values(raw.data() + off + pl * plane, o, n, h->cfg.state_dtype);
+    const size_t P = blk == 0 ? 5 : 3;
+    const size_t tile_bytes = P * M * kWave * h->esize;
+    // tiled [tile][param*M + rank][lane] -> canonical [param][rank][pixel]
+    for (size_t k = 0; k < P * M; ++k) {
+      for (size_t t = 0; t < h->tiles64; ++t) {
+        const size_t first = t * kWave;
+        const size_t cnt = std::min<size_t>(kWave, n - first);
+        unpack_values(raw.data() + off + t * tile_bytes + k * kWave * h->esize, o + first, cnt, h->cfg.state_dtype);
+      }
       o += n;
     }
-    off += plane * P * M;
+    off += tile_bytes * h->tiles64;
   }
   if (has_both(h)) {
     const uint8_t* f = raw.data() + off;
@@ -405,7 +410,6 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
 gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
   if (!h || !host_in) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
   const size_t n = static_cast<size_t>(h->npix), M = static_cast<size_t>(h->cfg.M);
-  const size_t plane = static_cast<size_t>(h->stride) * h->esize;
   const size_t total = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
   std::vector<uint8_t> raw;
   try {
@@ -418,12 +422,18 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
   for (int blk = 0; blk < 2; ++blk) {
     const bool present = blk == 0 ? has_rgb(h) : has_depth(h);
     if (!present) continue;
-    const int P = blk == 0 ? 5 : 3;
-    for (size_t pl = 0; pl < P * M; ++pl) {
-      pack_values(in, raw.data() + off + pl * plane, n, h->cfg.state_dtype);
+    const size_t P = blk == 0 ? 5 : 3;
+    const size_t tile_bytes = P * M * kWave * h->esize;
+    // canonical [param][rank][pixel] -> tiled [tile][param*M + rank][lane]
+    for (size_t k = 0; k < P * M; ++k) {
+      for (size_t t = 0; t < h->tiles64; ++t) {
+        const size_t first = t * kWave;
+        const size_t cnt = std::min<size_t>(kWave, n - first);
+        pack_values(in + first, raw.data() + off + t * tile_bytes + k * kWave * h->esize, cnt, h->cfg.state_dtype);
+      }
       in += n;
     }
-    off += plane * P * M;
+    off += tile_bytes * h->tiles64;
   }
   if (has_both(h)) {
     uint8_t* f = raw.data() + off;

@@ -65,24 +65,29 @@ struct Mix {
   float w[M];
 };
 
-// One modality's state block as a buffer resource. Plane order inside the block: mu channel
-// 0..C-1, var, w; each plane holds M rank-major sub-planes of `stride` pixels. A lane's byte
-// offset lives in one VGPR; the plane offset is a wave-uniform scalar (soffset), so every state
-// access is a single buffer instruction with no per-lane address arithmetic. The range checked
-// by the hardware (num_records) is the whole block - on gfx950 the scalar offset counts toward
-// it - so an access outside the block reads 0 and drops its write instead of touching other
-// memory. The host keeps every block below 4 GiB.
+// One modality's state block as a buffer resource, in a tiled structure-of-arrays layout:
+// pixels are grouped in tiles of 64 (one wave); a tile stores its P*M planes back to back
+// (plane order: mu channel 0..C-1, var, w; each parameter M rank-major planes), each plane-row
+// holding the tile's 64 values. A wave's accesses therefore stay one coalesced 64-value segment
+// per instruction AND fall in one contiguous region per tile (P*M*64 values), instead of P*M
+// regions spread over the whole frame. A lane's tile+lane byte offset lives in one VGPR and the
+// plane offset is a compile-time immediate, so every state access is one buffer instruction.
+// The range checked by the hardware (num_records) is the whole block: an access outside it reads
+// 0 and drops its write instead of touching other memory. The host keeps every block < 4 GiB.
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
 
 struct StateBlock {
   __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t plane_bytes;
+  uint32_t tile_bytes;  // P*M*64*sizeof(S)
 };
 
-__device__ __forceinline__ StateBlock make_block(void* base, int64_t stride, int esize, int planes) {
-  const uint32_t pb = static_cast<uint32_t>(stride * esize);
-  const uint32_t total = pb * static_cast<uint32_t>(planes);
-  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(total), kRsrcWord3), pb};
+__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, int esize, int planes) {
+  const uint32_t tb = static_cast<uint32_t>(planes * kWave * esize);
+  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(tb * tiles64), kRsrcWord3), tb};
+}
+
+__device__ __forceinline__ uint32_t lane_offset(const StateBlock& b, uint32_t p, uint32_t esize) {
+  return (p >> 6) * b.tile_bytes + (p & 63u) * esize;
 }
 
 template <typename S> struct BufIO;
@@ -114,28 +119,32 @@ template <> struct BufIO<bf16s> {
 
 template <int M, int C, typename S>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  const uint32_t off = p * static_cast<uint32_t>(sizeof(S));
+  constexpr uint32_t es = sizeof(S);
+  constexpr uint32_t row = kWave * es;  // bytes of one plane-row of a tile
+  const uint32_t off = lane_offset(b, p, es);
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int r = 0; r < M; ++r) m.mu[c][r] = Storage<S>::load(BufIO<S>::ld(b, off, (c * M + r) * b.plane_bytes));
+    for (int r = 0; r < M; ++r) m.mu[c][r] = Storage<S>::load(BufIO<S>::ld(b, off + (c * M + r) * row, 0));
 #pragma unroll
-  for (int r = 0; r < M; ++r) m.var[r] = Storage<S>::load(BufIO<S>::ld(b, off, (C * M + r) * b.plane_bytes));
+  for (int r = 0; r < M; ++r) m.var[r] = Storage<S>::load(BufIO<S>::ld(b, off + (C * M + r) * row, 0));
 #pragma unroll
-  for (int r = 0; r < M; ++r) m.w[r] = Storage<S>::load(BufIO<S>::ld(b, off, ((C + 1) * M + r) * b.plane_bytes));
+  for (int r = 0; r < M; ++r) m.w[r] = Storage<S>::load(BufIO<S>::ld(b, off + ((C + 1) * M + r) * row, 0));
 }
 
 template <int M, int C, typename S>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  const uint32_t off = p * static_cast<uint32_t>(sizeof(S));
+  constexpr uint32_t es = sizeof(S);
+  constexpr uint32_t row = kWave * es;
+  const uint32_t off = lane_offset(b, p, es);
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int r = 0; r < M; ++r) BufIO<S>::st(b, off, (c * M + r) * b.plane_bytes, Storage<S>::pack(m.mu[c][r]));
+    for (int r = 0; r < M; ++r) BufIO<S>::st(b, off + (c * M + r) * row, 0, Storage<S>::pack(m.mu[c][r]));
 #pragma unroll
-  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off, (C * M + r) * b.plane_bytes, Storage<S>::pack(m.var[r]));
+  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off + (C * M + r) * row, 0, Storage<S>::pack(m.var[r]));
 #pragma unroll
-  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off, ((C + 1) * M + r) * b.plane_bytes, Storage<S>::pack(m.w[r]));
+  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off + ((C + 1) * M + r) * row, 0, Storage<S>::pack(m.w[r]));
 }
 
 template <typename T>

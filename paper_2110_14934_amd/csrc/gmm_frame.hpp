@@ -60,7 +60,7 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);
     if (valid) {
       Mix<M, 3> m;
-      const StateBlock blk = make_block(a.st_rgb, a.stride, sizeof(S), 5 * M);
+      const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
       load_mix<M, 3, S>(m, blk, p);
       fgc = mix_step<M, 3>(m, x, a.kc);
       store_mix<M, 3, S>(m, blk, p);
@@ -73,7 +73,7 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
       const float xd = load_depth_pixel(a, p);
       if (!(a.kd.hole_skip && xd == 0.f)) {
         Mix<M, 1> m;
-        const StateBlock blk = make_block(a.st_depth, a.stride, sizeof(S), 3 * M);
+        const StateBlock blk = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
         load_mix<M, 1, S>(m, blk, p);
         const float x1[1] = {xd};
         fgd = mix_step<M, 1>(m, x1, a.kd);

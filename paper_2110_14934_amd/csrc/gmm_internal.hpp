@@ -14,7 +14,8 @@ namespace rgbd {
 // Everything one frame-kernel launch needs for one stream.
 struct FrameArgs {
   int64_t npix;
-  int64_t stride;          // elements between consecutive state planes (npix rounded up to 64)
+  uint32_t tiles64;        // 64-pixel tiles of the state layout (ceil(npix / 64))
+  uint32_t pad0_;
   int32_t width;
   int32_t rgb_dense;       // rgb rows are contiguous (pitch == 3*width) and 4-byte aligned
   int32_t depth_dense;     // depth rows are contiguous (pitch == 2*width)
@@ -40,7 +41,7 @@ enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4 };
 hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStream_t s);
 hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, uint8_t* fstate,
                        int64_t npix, hipStream_t s);
-hipError_t launch_init(void* st, int dtype, int64_t stride, int M, int C, float var0, hipStream_t s);
+hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 
 bool frame_variant_compiled(int M, int dtype);
@@ -75,7 +76,7 @@ class DeviceGuard {
 struct gmm_handle {  // the library's per-stream object (opaque in gmm.h)
   gmm_config cfg;
   int64_t npix = 0;
-  int64_t stride = 0;       // elements per plane
+  uint32_t tiles64 = 0;     // 64-pixel tiles of the state layout
   size_t esize = 0;         // bytes per stored value
   size_t rgb_bytes = 0;     // colour block
   size_t depth_bytes = 0;   // depth block

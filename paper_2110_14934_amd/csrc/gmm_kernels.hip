@@ -44,14 +44,14 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
   if (lane == 0 && valid) out[word] = bits;
 }
 
-// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks).
+// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks), tiled layout.
 template <typename S>
-__global__ void __launch_bounds__(kBlock) init_kernel(S* st, int64_t stride, int M, int C,
-                                                      float var0) {
+__global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, int M, int C, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t total = static_cast<int64_t>(C + 2) * M * stride;
+  const int64_t planes = static_cast<int64_t>(C + 2) * M;
+  const int64_t total = planes * kWave * tiles64;
   if (i >= total) return;
-  const int64_t plane = i / stride;
+  const int64_t plane = (i / kWave) % planes;
   const int64_t param = plane / M;
   st[i] = Storage<S>::pack(param == C ? var0 : 0.f);
 }
@@ -113,13 +113,13 @@ hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, ui
   return hipGetLastError();
 }
 
-hipError_t launch_init(void* st, int dtype, int64_t stride, int M, int C, float var0, hipStream_t s) {
-  const int64_t total = static_cast<int64_t>(C + 2) * M * stride;
+hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(C + 2) * M * kWave * tiles64;
   const dim3 g = grid_for(total), b(kBlock);
   switch (dtype) {
-    case GMM_F32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float*>(st), stride, M, C, var0); break;
-    case GMM_F16: init_kernel<f16s><<<g, b, 0, s>>>(static_cast<f16s*>(st), stride, M, C, var0); break;
-    case GMM_BF16: init_kernel<bf16s><<<g, b, 0, s>>>(static_cast<bf16s*>(st), stride, M, C, var0); break;
+    case GMM_F32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float*>(st), tiles64, M, C, var0); break;
+    case GMM_F16: init_kernel<f16s><<<g, b, 0, s>>>(static_cast<f16s*>(st), tiles64, M, C, var0); break;
+    case GMM_BF16: init_kernel<bf16s><<<g, b, 0, s>>>(static_cast<bf16s*>(st), tiles64, M, C, var0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
