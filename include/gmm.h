@@ -235,6 +235,66 @@ gmm_status gmm_batch_autotune(gmm_batch* b, int32_t slot, void* stream, gmm_batc
 /* Number of tiles of one launch under the current tuning. */
 gmm_status gmm_batch_tiles(const gmm_batch* b, uint32_t* n_tiles);
 
+/* ---- serving executor: ticks of host frames through one batched launch each --------------- */
+
+typedef struct gmm_exec gmm_exec;
+
+/* One stream's frame in a tick. Frames are read from host memory with dense rows (pitch
+ * 3*width for colour, 2*width for depth); masks are written to host memory. Host buffers should
+ * be pinned (page-locked) for the copies to overlap; they must stay valid and untouched until
+ * the tick completes (gmm_exec_poll). A NULL mask pointer skips copying that mask back;
+ * non-NULL host_fused runs List 1 for the stream (two-modality streams only). */
+typedef struct {
+  gmm_handle* handle;
+  const uint8_t* host_rgb;
+  const uint16_t* host_depth;
+  uint64_t* host_fg_rgb;
+  uint64_t* host_fg_depth;
+  uint64_t* host_fused;
+} gmm_exec_item;
+
+/*
+ * Executor for the serving loop: three default-priority streams (copy-in, compute, copy-out)
+ * pipeline consecutive ticks as in the paper's overlap of host transfers with device work
+ * (Sec. IV, Fig. 4(a)); `ring` (1..64) bounds the ticks in flight. A completion thread records
+ * each tick's completion time on the gmm_exec_now() clock.
+ */
+gmm_status gmm_exec_create(int32_t device, int32_t ring, gmm_exec** out);
+/* Wait for all ticks, then release. NULL is a no-op. Attached handles stay valid. */
+gmm_status gmm_exec_destroy(gmm_exec* x);
+/* Launch shape of the batched kernel (same meaning and limits as gmm_batch_tuning). */
+gmm_status gmm_exec_set_tuning(gmm_exec* x, const gmm_batch_tuning* t);
+/* Give a stream a device frame slot and device masks (all streams of an executor share M and
+ * the state dtype). Reports the device bytes this adds, for memory admission. */
+gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes);
+/* Release a stream's slot after its last tick has completed (waits for it). */
+gmm_status gmm_exec_detach(gmm_exec* x, gmm_handle* h);
+/*
+ * Advance the given streams (each at most once, none with a frame still in flight) by one frame
+ * in one tick; returns at once with the tick's id (ids increase by 1 from 1). Blocks only when
+ * `ring` ticks are already in flight. Per stream, masks and state are bit-identical to
+ * gmm_apply_frame / gmm_apply_frame_fused on the same frame.
+ */
+gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, uint64_t* tick_id);
+/* Completed ticks since the last poll, in launch order: ids and completion times (at most cap). */
+gmm_status gmm_exec_poll(gmm_exec* x, uint64_t* tick_ids, double* t_done, int32_t cap, int32_t* n);
+/* Block until every launched tick has completed. */
+gmm_status gmm_exec_drain(gmm_exec* x);
+/* The executor clock: seconds on a monotonic clock. */
+double gmm_exec_now(void);
+
+/* ---- evaluation ------------------------------------------------------------------------- */
+
+/*
+ * Confusion counts of a predicted foreground mask against a reference mask, the quantities
+ * recall, precision and F1 are computed from (Sec. V.A, Eqs. 1-3): counts[0..3] = TP, FP, TN,
+ * FN over the first npix pixels (pad bits ignored). pred, truth: device bit-packed masks in the
+ * layout above; counts: device array of 4 uint64, overwritten (not accumulated). Asynchronous
+ * on `stream`; no allocation.
+ */
+gmm_status gmm_mask_confusion(const uint64_t* pred, const uint64_t* truth, int64_t npix, uint64_t* counts,
+                              void* stream);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t gmm_version(void);
 

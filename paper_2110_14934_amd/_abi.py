@@ -35,6 +35,9 @@ EXPORTS = (
     "gmm_read_state", "gmm_write_state", "gmm_version",
     "gmm_batch_create", "gmm_batch_destroy", "gmm_batch_set_tuning", "gmm_batch_get_tuning",
     "gmm_batch_set_frames", "gmm_batch_run", "gmm_batch_apply", "gmm_batch_autotune", "gmm_batch_tiles",
+    "gmm_mask_confusion",
+    "gmm_exec_create", "gmm_exec_destroy", "gmm_exec_set_tuning", "gmm_exec_attach", "gmm_exec_detach",
+    "gmm_exec_launch", "gmm_exec_poll", "gmm_exec_drain", "gmm_exec_now",
 )
 
 
@@ -69,6 +72,13 @@ class gmm_batch_tuning(ctypes.Structure):
 
     def as_tuple(self):
         return (self.block_threads, self.tile_pixels, self.blocks_per_cu)
+
+
+class gmm_exec_item(ctypes.Structure):
+    _fields_ = [
+        ("handle", ctypes.c_void_p), ("host_rgb", ctypes.c_void_p), ("host_depth", ctypes.c_void_p),
+        ("host_fg_rgb", ctypes.c_void_p), ("host_fg_depth", ctypes.c_void_p), ("host_fused", ctypes.c_void_p),
+    ]
 
 
 _lib = None
@@ -109,6 +119,17 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "gmm_batch_autotune": (st, [H, ctypes.c_int32, vp, ctypes.POINTER(gmm_batch_tuning),
                                     ctypes.POINTER(ctypes.c_double)]),
         "gmm_batch_tiles": (st, [H, ctypes.POINTER(ctypes.c_uint32)]),
+        "gmm_mask_confusion": (st, [vp, vp, i64, vp, vp]),
+        "gmm_exec_create": (st, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(H)]),
+        "gmm_exec_destroy": (st, [H]),
+        "gmm_exec_set_tuning": (st, [H, ctypes.POINTER(gmm_batch_tuning)]),
+        "gmm_exec_attach": (st, [H, H, ctypes.POINTER(ctypes.c_size_t)]),
+        "gmm_exec_detach": (st, [H, H]),
+        "gmm_exec_launch": (st, [H, ctypes.POINTER(gmm_exec_item), ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+        "gmm_exec_poll": (st, [H, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32)]),
+        "gmm_exec_drain": (st, [H]),
+        "gmm_exec_now": (ctypes.c_double, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -276,3 +297,60 @@ def gmm_batch_tiles(b) -> int:
     n = ctypes.c_uint32()
     _check(load().gmm_batch_tiles(b, ctypes.byref(n)))
     return n.value
+
+
+def gmm_mask_confusion(pred, truth, npix: int, counts, stream=None):
+    """TP, FP, TN, FN of two bit-packed device masks into `counts` (4 int64, device)."""
+    _check(load().gmm_mask_confusion(_ptr(pred), _ptr(truth), npix, _ptr(counts), _stream(stream)))
+
+
+# ---- serving executor --------------------------------------------------------------------
+
+def gmm_exec_create(device: int = 0, ring: int = 4) -> int:
+    x = ctypes.c_void_p()
+    _check(load().gmm_exec_create(device, ring, ctypes.byref(x)))
+    return x.value
+
+
+def gmm_exec_destroy(x):
+    _check(load().gmm_exec_destroy(x))
+
+
+def gmm_exec_set_tuning(x, block_threads: int, tile_pixels: int, blocks_per_cu: int):
+    t = gmm_batch_tuning(block_threads, tile_pixels, blocks_per_cu)
+    _check(load().gmm_exec_set_tuning(x, ctypes.byref(t)))
+
+
+def gmm_exec_attach(x, h) -> int:
+    n = ctypes.c_size_t()
+    _check(load().gmm_exec_attach(x, h, ctypes.byref(n)))
+    return n.value
+
+
+def gmm_exec_detach(x, h):
+    _check(load().gmm_exec_detach(x, h))
+
+
+def gmm_exec_launch(x, items) -> int:
+    """items: list of gmm_exec_item (host pointers as ints)."""
+    arr = (gmm_exec_item * len(items))(*items)
+    tid = ctypes.c_uint64()
+    _check(load().gmm_exec_launch(x, arr, len(items), ctypes.byref(tid)))
+    return tid.value
+
+
+def gmm_exec_poll(x, cap: int = 256):
+    """[(tick id, completion time)] of ticks completed since the last poll, in launch order."""
+    ids = (ctypes.c_uint64 * cap)()
+    ts = (ctypes.c_double * cap)()
+    n = ctypes.c_int32()
+    _check(load().gmm_exec_poll(x, ids, ts, cap, ctypes.byref(n)))
+    return [(ids[i], ts[i]) for i in range(n.value)]
+
+
+def gmm_exec_drain(x):
+    _check(load().gmm_exec_drain(x))
+
+
+def gmm_exec_now() -> float:
+    return load().gmm_exec_now()

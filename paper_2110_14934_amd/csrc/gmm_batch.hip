@@ -74,7 +74,7 @@ static hipError_t launch_batch_s(int M, int block, dim3 grid, const FrameArgs* t
   }
 }
 
-static hipError_t launch_batch(int M, int dtype, int block, dim3 grid, const FrameArgs* table,
+hipError_t launch_batch(int M, int dtype, int block, dim3 grid, const FrameArgs* table,
                                const uint32_t* map, const uint32_t* first, uint32_t n_tiles,
                                uint32_t tile_px, hipStream_t s) {
   switch (dtype) {

@@ -45,6 +45,8 @@ hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, floa
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 
 bool frame_variant_compiled(int M, int dtype);
+hipError_t launch_batch(int M, int dtype, int block, dim3 grid, const FrameArgs* table, const uint32_t* map,
+                        const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, hipStream_t s);
 
 inline size_t dtype_size(int dtype) { return dtype == GMM_F32 ? 4 : 2; }
 

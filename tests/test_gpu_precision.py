@@ -1,0 +1,104 @@
+"""Reduced-precision mixture state (fp16 / bf16 storage, fp32 arithmetic) against fp32 state
+and the FP64 oracle, free running over the 120-frame clip of 16 streams of the 256-stream
+640x480 workload. Reports, per storage type, the parameter error and the mask disagreement."""
+import json
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import MixParams, MixtureOracle
+from paper_2110_14934_amd import GMM_RGB, GMM_DEPTH, Batch, Segmenter
+from paper_2110_14934_amd.synth import Stream, workload
+from tests.parity import unpack_mask, from_canonical
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+N_STREAMS = 16
+N_PIX = 512
+
+
+def _params(mix, modality):
+    if modality == "rgb":
+        return MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_rgb, mix.var_min_rgb, mix.w_init)
+    return MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_depth, mix.var_min_depth, mix.w_init, hole_skip=True)
+
+
+def _rel_err(g, o, floor):
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), floor)))
+
+
+def test_reduced_precision_report():
+    wl = workload("precision-256")
+    mix = wl.mix
+    specs = wl.streams[:N_STREAMS]
+    streams = [Stream(s) for s in specs]
+    dtypes = ("f32", "f16", "bf16")
+    segs = {d: [Segmenter(s.width, s.height, GMM_RGB | GMM_DEPTH, mix.M, state_dtype=d) for s in specs] for d in dtypes}
+    batches = {d: Batch(segs[d]) for d in dtypes}
+    rng = np.random.default_rng(23)
+    n = specs[0].npix
+    samples = [np.sort(rng.choice(n, N_PIX, replace=False)) for _ in specs]
+    col = [MixtureOracle(_params(mix, "rgb"), 3, N_PIX) for _ in specs]
+    dep = [MixtureOracle(_params(mix, "depth"), 1, N_PIX) for _ in specs]
+    dis = {(d, ref, m): 0 for d in dtypes for ref in ("fp64", "f32") for m in ("rgb", "depth")}
+    total = 0
+    try:
+        for t in range(wl.frames):
+            frames = [(st.rgb(t, device=DEV), st.depth(t, device=DEV)) for st in streams]
+            for d in dtypes:
+                batches[d].apply(frames, fuse=False)
+            torch.cuda.synchronize()
+            for i, st in enumerate(streams):
+                pix = torch.from_numpy(samples[i])
+                oc = col[i].step(st.rgb(t, pix=pix).numpy()).fg
+                od = dep[i].step(st.depth(t, pix=pix).numpy()).fg
+                ref32 = {"rgb": unpack_mask(segs["f32"][i].fg_rgb, n)[samples[i]],
+                         "depth": unpack_mask(segs["f32"][i].fg_depth, n)[samples[i]]}
+                for d in dtypes:
+                    g = {"rgb": unpack_mask(segs[d][i].fg_rgb, n)[samples[i]],
+                         "depth": unpack_mask(segs[d][i].fg_depth, n)[samples[i]]}
+                    dis[(d, "fp64", "rgb")] += int((g["rgb"] != oc).sum())
+                    dis[(d, "fp64", "depth")] += int((g["depth"] != od).sum())
+                    dis[(d, "f32", "rgb")] += int((g["rgb"] != ref32["rgb"]).sum())
+                    dis[(d, "f32", "depth")] += int((g["depth"] != ref32["depth"]).sum())
+            total += N_STREAMS * N_PIX
+        report = {"frames": wl.frames, "streams": N_STREAMS, "pixels_per_stream": N_PIX}
+        states = {d: [from_canonical(s.read_state(), mix.M, n, True, True) for s in segs[d]] for d in dtypes}
+        for d in dtypes:
+            r = {}
+            for m in ("rgb", "depth"):
+                r[f"mask_disagreement_vs_fp64_{m}"] = dis[(d, "fp64", m)] / total
+                r[f"mask_disagreement_vs_f32_{m}"] = dis[(d, "f32", m)] / total
+                # parameter error of the top-ranked component (the background model) where both
+                # sides still hold the same component at rank 0
+                mu_err, var_err, w_err, same = [], [], [], 0
+                for i in range(N_STREAMS):
+                    gm, gv, gw = (a[..., samples[i]] for a in states[d][i][m])
+                    o = col[i] if m == "rgb" else dep[i]
+                    thr = 3.0 * np.sqrt(o.var[0])
+                    ok = np.all(np.abs(gm[0] - o.mu[0]) < thr, axis=0)
+                    same += int(ok.sum())
+                    mu_err.append(np.max(np.abs(gm[0][:, ok] - o.mu[0][:, ok]) / np.maximum(np.abs(o.mu[0][:, ok]), 1.0), initial=0))
+                    var_err.append(np.max(np.abs(gv[0][ok] - o.var[0][ok]) / o.var[0][ok], initial=0))
+                    w_err.append(np.max(np.abs(gw[0][ok] - o.w[0][ok]) / np.maximum(o.w[0][ok], 1e-3), initial=0))
+                r[f"rank0_same_component_{m}"] = same / (N_STREAMS * N_PIX)
+                r[f"rank0_mu_max_rel_err_{m}"] = float(max(mu_err))
+                r[f"rank0_var_max_rel_err_{m}"] = float(max(var_err))
+                r[f"rank0_w_max_rel_err_{m}"] = float(max(w_err))
+            report[d] = r
+        print("PRECISION_REPORT " + json.dumps(report), flush=True)
+        sys.stdout.flush()
+        # fp32 state matches the oracle to the free-run bound; reduced precision stays usable
+        assert report["f32"]["mask_disagreement_vs_fp64_rgb"] <= 1e-3
+        assert report["f32"]["mask_disagreement_vs_fp64_depth"] <= 1e-3
+        for d in ("f16", "bf16"):
+            for m in ("rgb", "depth"):
+                assert report[d][f"mask_disagreement_vs_fp64_{m}"] < 0.25, (d, m)
+                assert report[d][f"rank0_same_component_{m}"] > 0.5, (d, m)
+    finally:
+        for d in dtypes:
+            batches[d].close()
+            for s in segs[d]:
+                s.close()

@@ -1,0 +1,63 @@
+"""Segmentation quality on the GPU (Sec. V.A, Eqs. 1-3) over the 640x480 clip with its
+illumination ramp: a directional analogue of the paper's ordinary-scene experiment (its
+captures are not available, so the numbers are not comparable to its figures)."""
+import json
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics
+from paper_2110_14934_amd import GMM_RGB, GMM_DEPTH, Segmenter
+from paper_2110_14934_amd.quality import confusion, pack_mask
+from paper_2110_14934_amd.synth import Stream, workload
+from tests.parity import unpack_mask
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+@pytest.mark.parametrize("npix", [1, 63, 64, 65, 4097, 307200])
+def test_confusion_counts_match_oracle(npix):
+    rng = np.random.default_rng(npix)
+    pred = rng.random(npix) < 0.3
+    truth = rng.random(npix) < 0.2
+    pw = pack_mask(torch.from_numpy(pred).to(DEV))
+    tw = pack_mask(torch.from_numpy(truth).to(DEV))
+    # stray pad bits must not count
+    if npix % 64:
+        pw[-1] |= torch.tensor(-1 << (npix % 64), dtype=torch.int64, device=DEV)
+    c = confusion(pw, tw, npix)
+    assert (c.tp, c.fp, c.tn, c.fn) == metrics.confusion(pred, truth)
+    assert np.array_equal(unpack_mask(pack_mask(torch.from_numpy(pred).to(DEV)), npix), pred)
+
+
+def test_quality_over_illumination_ramp():
+    wl = workload("plain-640x480")
+    spec, mix = wl.streams[0], wl.mix
+    st = Stream(spec)
+    n = spec.npix
+    seg = Segmenter(spec.width, spec.height, GMM_RGB | GMM_DEPTH, mix.M)
+    f1 = {"rgb": [], "depth": [], "fused": []}
+    try:
+        for t in range(wl.frames):
+            seg.apply_fused(st.rgb(t, device=DEV), st.depth(t, device=DEV))
+            truth = pack_mask(st.truth(t, device=DEV))
+            for name, words in (("rgb", seg.fg_rgb), ("depth", seg.fg_depth), ("fused", seg.fused)):
+                c = confusion(words, truth, n)
+                f1[name].append(c.f1)
+                if t % 50 == 25:   # the device counts equal the oracle's on the unpacked masks
+                    ref = metrics.confusion(unpack_mask(words, n), st.truth(t).reshape(-1).numpy())
+                    assert (c.tp, c.fp, c.tn, c.fn) == ref, (name, t)
+    finally:
+        seg.close()
+    win = {"before": (20, 100), "ramp": (100, 151), "after": (160, 300)}
+    rep = {k: {w: float(np.nanmean(v[a:b])) for w, (a, b) in win.items()} for k, v in f1.items()}
+    rep["rgb_min_ramp"] = float(np.nanmin(f1["rgb"][100:151]))
+    print("QUALITY_REPORT " + json.dumps(rep), flush=True)
+    sys.stdout.flush()
+    # illumination change hurts colour, not depth; the fused mask holds up better than colour
+    assert rep["rgb"]["ramp"] < rep["rgb"]["before"] - 0.05
+    assert abs(rep["depth"]["ramp"] - rep["depth"]["before"]) < 0.1
+    assert rep["fused"]["ramp"] > rep["rgb"]["ramp"]
