@@ -112,14 +112,15 @@ def bench_batch(args) -> int:
     dtype = args.state_dtype or wl.state_dtype
     esize = 4 if dtype == "f32" else 2
     M = wl.mix.M
-    F = args.clip or (wl.frames if args.workload == "batch-64" else 24)
+    F = args.clip or args.host_frames or (wl.frames if args.workload == "batch-64" else 24)
     streams = [Stream(sp) for sp in wl.streams]
     frames, holes = [], []
+    gen_dev = "cpu" if args.host_frames else dev   # host frames: few GPU dispatches (counter runs)
     for t in range(F):
         fs, hs = [], []
         for st in streams:
-            rgb = st.rgb(t, device=dev) if st.spec.rgb else None
-            dep = st.depth(t, device=dev) if st.spec.depth else None
+            rgb = st.rgb(t, device=gen_dev).to(dev) if st.spec.rgb else None
+            dep = st.depth(t, device=gen_dev).to(dev) if st.spec.depth else None
             fs.append((rgb, dep))
             hs.append((dep == 0).sum() if dep is not None else torch.zeros((), device=dev, dtype=torch.int64))
         frames.append(fs)

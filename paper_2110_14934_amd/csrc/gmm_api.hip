@@ -387,12 +387,14 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     if (!present) continue;
     const size_t P = blk == 0 ? 5 : 3;
     const size_t tile_bytes = P * M * kWave * h->esize;
-    // tiled [tile][param*M + rank][lane] -> canonical [param][rank][pixel]
+    // tiled device layout -> canonical [param][rank][pixel]
+    const uint32_t nv = static_cast<uint32_t>(P * M);
     for (size_t k = 0; k < P * M; ++k) {
-      for (size_t t = 0; t < h->tiles64; ++t) {
-        const size_t first = t * kWave;
-        const size_t cnt = std::min<size_t>(kWave, n - first);
-        unpack_values(raw.data() + off + t * tile_bytes + k * kWave * h->esize, o + first, cnt, h->cfg.state_dtype);
+      for (size_t i = 0; i < n; ++i) {
+        const size_t at = off + (i / kWave) * tile_bytes +
+                          tile_value_offset(static_cast<uint32_t>(k), static_cast<uint32_t>(i % kWave), nv,
+                                            static_cast<uint32_t>(h->esize));
+        unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
       }
       o += n;
     }
@@ -424,12 +426,14 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     if (!present) continue;
     const size_t P = blk == 0 ? 5 : 3;
     const size_t tile_bytes = P * M * kWave * h->esize;
-    // canonical [param][rank][pixel] -> tiled [tile][param*M + rank][lane]
+    // canonical [param][rank][pixel] -> tiled device layout
+    const uint32_t nv = static_cast<uint32_t>(P * M);
     for (size_t k = 0; k < P * M; ++k) {
-      for (size_t t = 0; t < h->tiles64; ++t) {
-        const size_t first = t * kWave;
-        const size_t cnt = std::min<size_t>(kWave, n - first);
-        pack_values(in + first, raw.data() + off + t * tile_bytes + k * kWave * h->esize, cnt, h->cfg.state_dtype);
+      for (size_t i = 0; i < n; ++i) {
+        const size_t at = off + (i / kWave) * tile_bytes +
+                          tile_value_offset(static_cast<uint32_t>(k), static_cast<uint32_t>(i % kWave), nv,
+                                            static_cast<uint32_t>(h->esize));
+        pack_values(in + i, raw.data() + at, 1, h->cfg.state_dtype);
       }
       in += n;
     }

@@ -65,16 +65,28 @@ struct Mix {
   float w[M];
 };
 
-// One modality's state block as a buffer resource, in a tiled structure-of-arrays layout:
-// pixels are grouped in tiles of 64 (one wave); a tile stores its P*M planes back to back
-// (plane order: mu channel 0..C-1, var, w; each parameter M rank-major planes), each plane-row
-// holding the tile's 64 values. A wave's accesses therefore stay one coalesced 64-value segment
-// per instruction AND fall in one contiguous region per tile (P*M*64 values), instead of P*M
-// regions spread over the whole frame. A lane's tile+lane byte offset lives in one VGPR and the
-// plane offset is a compile-time immediate, so every state access is one buffer instruction.
-// The range checked by the hardware (num_records) is the whole block: an access outside it reads
-// 0 and drops its write instead of touching other memory. The host keeps every block < 4 GiB.
+// One modality's state block as a buffer resource, in a tiled layout. Pixels are grouped in
+// tiles of 64 (one wave); each pixel has NV = P*M values (plane order: mu channel 0..C-1, var,
+// w; each parameter M ranks). Inside a tile, values are stored in 16-byte chunks per lane: chunk
+// c holds values [c*VPC, (c+1)*VPC) of all 64 lanes as [lane][VPC] (VPC = 16/sizeof(value)), so
+// one wave instruction moves 1 KB of contiguous memory; the NV % VPC values left over are
+// stored as single rows [lane]. A wave's accesses to one modality fall in one contiguous region
+// of NV*64 values, with no padding. A lane's tile + lane byte offset lives in one VGPR and the
+// chunk offsets are compile-time constants, so every state access is one buffer instruction.
+// The range checked by the hardware (num_records) is the whole block: an access outside it
+// reads 0 and drops its write instead of touching other memory. The host keeps every block
+// below 4 GiB.
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
+constexpr uint32_t kChunkBytes = 16;
+
+// Byte offset, inside its tile, of value v of lane `lane` (nv values per pixel, es bytes each).
+__host__ __device__ constexpr uint32_t tile_value_offset(uint32_t v, uint32_t lane, uint32_t nv, uint32_t es) {
+  const uint32_t vpc = kChunkBytes / es;
+  const uint32_t nc = nv / vpc;
+  const uint32_t nf = nc * vpc;
+  return v < nf ? (v / vpc) * (64u * kChunkBytes) + lane * kChunkBytes + (v % vpc) * es
+                : nc * (64u * kChunkBytes) + (v - nf) * 64u * es + lane * es;
+}
 
 struct StateBlock {
   __amdgpu_buffer_rsrc_t rsrc;
@@ -86,65 +98,106 @@ __device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, i
   return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(tb * tiles64), kRsrcWord3), tb};
 }
 
-__device__ __forceinline__ uint32_t lane_offset(const StateBlock& b, uint32_t p, uint32_t esize) {
-  return (p >> 6) * b.tile_bytes + (p & 63u) * esize;
-}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename S> struct BufIO;
 template <> struct BufIO<float> {
-  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off, uint32_t so) {
-    // the b32 builtins move raw 32-bit words: reinterpret, never convert
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, off, so, 0));
+  // the b32 builtins move raw 32-bit words: reinterpret, never convert
+  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, off, 0, 0));
   }
-  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, uint32_t so, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.rsrc, off, so, 0);
+  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.rsrc, off, 0, 0);
   }
+  static __device__ __forceinline__ float from_word(uint32_t w, int) { return __builtin_bit_cast(float, w); }
+  static __device__ __forceinline__ uint32_t word(const float* v) { return __builtin_bit_cast(uint32_t, v[0]); }
 };
 template <> struct BufIO<f16s> {
-  static __device__ __forceinline__ f16s ld(const StateBlock& b, uint32_t off, uint32_t so) {
-    return f16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, so, 0)};
+  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
+    return Storage<f16s>::load(f16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, 0, 0)});
   }
-  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, uint32_t so, f16s v) {
-    __builtin_amdgcn_raw_buffer_store_b16(v.b, b.rsrc, off, so, 0);
+  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(Storage<f16s>::pack(v).b, b.rsrc, off, 0, 0);
+  }
+  // a word holds two values, the lower-addressed one in the low half
+  static __device__ __forceinline__ float from_word(uint32_t w, int half) {
+    return Storage<f16s>::load(f16s{static_cast<uint16_t>(half ? (w >> 16) : (w & 0xFFFFu))});
+  }
+  static __device__ __forceinline__ uint32_t word(const float* v) {
+    return static_cast<uint32_t>(Storage<f16s>::pack(v[0]).b) | (static_cast<uint32_t>(Storage<f16s>::pack(v[1]).b) << 16);
   }
 };
 template <> struct BufIO<bf16s> {
-  static __device__ __forceinline__ bf16s ld(const StateBlock& b, uint32_t off, uint32_t so) {
-    return bf16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, so, 0)};
+  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
+    return Storage<bf16s>::load(bf16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, 0, 0)});
   }
-  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, uint32_t so, bf16s v) {
-    __builtin_amdgcn_raw_buffer_store_b16(v.b, b.rsrc, off, so, 0);
+  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(Storage<bf16s>::pack(v).b, b.rsrc, off, 0, 0);
+  }
+  static __device__ __forceinline__ float from_word(uint32_t w, int half) {
+    return __builtin_bit_cast(float, half ? (w & 0xFFFF0000u) : (w << 16));
+  }
+  static __device__ __forceinline__ uint32_t word(const float* v) {
+    return static_cast<uint32_t>(Storage<bf16s>::pack(v[0]).b) | (static_cast<uint32_t>(Storage<bf16s>::pack(v[1]).b) << 16);
   }
 };
 
+// All NV values of pixel p (16-byte chunks, then single values).
+template <int NV, typename S>
+__device__ __forceinline__ void load_values(float (&v)[NV], const StateBlock& b, uint32_t p) {
+  constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc, vpw = 4 / es;
+  const uint32_t lane = p & 63u;
+  const uint32_t base = (p >> 6) * b.tile_bytes;
+#pragma unroll
+  for (uint32_t c = 0; c < nc; ++c) {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
+#pragma unroll
+    for (uint32_t i = 0; i < vpc; ++i) v[c * vpc + i] = BufIO<S>::from_word(w[i / vpw], static_cast<int>(i % vpw));
+  }
+#pragma unroll
+  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j) v[j] = BufIO<S>::ld(b, base + tile_value_offset(j, lane, NV, es));
+}
+
+template <int NV, typename S>
+__device__ __forceinline__ void store_values(const float (&v)[NV], const StateBlock& b, uint32_t p) {
+  constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc, vpw = 4 / es;
+  const uint32_t lane = p & 63u;
+  const uint32_t base = (p >> 6) * b.tile_bytes;
+#pragma unroll
+  for (uint32_t c = 0; c < nc; ++c) {
+    u32x4 w;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) w[i] = BufIO<S>::word(&v[c * vpc + i * vpw]);
+    __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
+  }
+#pragma unroll
+  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j) BufIO<S>::st(b, base + tile_value_offset(j, lane, NV, es), v[j]);
+}
+
 template <int M, int C, typename S>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr uint32_t es = sizeof(S);
-  constexpr uint32_t row = kWave * es;  // bytes of one plane-row of a tile
-  const uint32_t off = lane_offset(b, p, es);
+  float v[(C + 2) * M];
+  load_values<(C + 2) * M, S>(v, b, p);
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+  for (int r = 0; r < M; ++r) {
 #pragma unroll
-    for (int r = 0; r < M; ++r) m.mu[c][r] = Storage<S>::load(BufIO<S>::ld(b, off + (c * M + r) * row, 0));
-#pragma unroll
-  for (int r = 0; r < M; ++r) m.var[r] = Storage<S>::load(BufIO<S>::ld(b, off + (C * M + r) * row, 0));
-#pragma unroll
-  for (int r = 0; r < M; ++r) m.w[r] = Storage<S>::load(BufIO<S>::ld(b, off + ((C + 1) * M + r) * row, 0));
+    for (int c = 0; c < C; ++c) m.mu[c][r] = v[c * M + r];
+    m.var[r] = v[C * M + r];
+    m.w[r] = v[(C + 1) * M + r];
+  }
 }
 
 template <int M, int C, typename S>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr uint32_t es = sizeof(S);
-  constexpr uint32_t row = kWave * es;
-  const uint32_t off = lane_offset(b, p, es);
+  float v[(C + 2) * M];
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+  for (int r = 0; r < M; ++r) {
 #pragma unroll
-    for (int r = 0; r < M; ++r) BufIO<S>::st(b, off + (c * M + r) * row, 0, Storage<S>::pack(m.mu[c][r]));
-#pragma unroll
-  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off + (C * M + r) * row, 0, Storage<S>::pack(m.var[r]));
-#pragma unroll
-  for (int r = 0; r < M; ++r) BufIO<S>::st(b, off + ((C + 1) * M + r) * row, 0, Storage<S>::pack(m.w[r]));
+    for (int c = 0; c < C; ++c) v[c * M + r] = m.mu[c][r];
+    v[C * M + r] = m.var[r];
+    v[(C + 1) * M + r] = m.w[r];
+  }
+  store_values<(C + 2) * M, S>(v, b, p);
 }
 
 template <typename T>

@@ -48,12 +48,15 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
 template <typename S>
 __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, int M, int C, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t planes = static_cast<int64_t>(C + 2) * M;
-  const int64_t total = planes * kWave * tiles64;
+  const uint32_t nv = static_cast<uint32_t>((C + 2) * M);
+  const int64_t total = static_cast<int64_t>(nv) * kWave * tiles64;
   if (i >= total) return;
-  const int64_t plane = (i / kWave) % planes;
-  const int64_t param = plane / M;
-  st[i] = Storage<S>::pack(param == C ? var0 : 0.f);
+  const uint32_t lane = static_cast<uint32_t>(i % kWave);
+  const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
+  const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
+  const int64_t byte = tile * nv * kWave * static_cast<int64_t>(sizeof(S)) + tile_value_offset(v, lane, nv, sizeof(S));
+  const uint32_t param = v / static_cast<uint32_t>(M);
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(param == static_cast<uint32_t>(C) ? var0 : 0.f);
 }
 
 __global__ void __launch_bounds__(kBlock) fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
