@@ -216,12 +216,13 @@ def bench_serve(args) -> int:
         pools[(k.width, k.height, k.modalities)] = [
             (st.rgb(t).contiguous().pin_memory() if rgb else None,
              st.depth(t).contiguous().pin_memory() if dep else None) for t in range(8)]
-    ex = NativeExecutor(ring=4, state_dtype=dtype, tuning=(256, 1024, 4))
-    srv = Server(ex, int(args.serve_budget_gb * (1 << 30)), max_queue=8)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    ex = NativeExecutor(ring=4, state_dtype=dtype, tuning=(256, 1024, 4), arena_bytes=budget)
+    srv = Server(ex, budget, max_queue=8)
     prog = lambda m: print("[serve] " + m, file=sys.stderr, flush=True)
     try:
         rep = run_load(srv, pools, n_streams=args.serve_streams, duration_s=args.serve_seconds,
-                       churn_per_s=1.0, warmup_s=min(2.0, args.serve_seconds / 4), progress=prog)
+                       churn_per_s=args.serve_churn, warmup_s=min(2.0, args.serve_seconds / 4), progress=prog)
     finally:
         srv.close()
         ex.close()
@@ -231,7 +232,7 @@ def bench_serve(args) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded Kinect-shaped streams replayed from pinned pools)",
         "config": {"workload": "serve-1024", "streams": args.serve_streams, "state_dtype": dtype,
-                   "seconds": args.serve_seconds, "budget_gb": args.serve_budget_gb},
+                   "seconds": args.serve_seconds, "budget_gb": args.serve_budget_gb, "churn_per_s": args.serve_churn},
         "latency_ms": {"p50": rep["p50_latency_ms"], "p99": rep["p99_latency_ms"], "max": rep["max_latency_ms"]},
         "serve": rep,
     }
@@ -255,6 +256,7 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="serving run length")
     ap.add_argument("--serve-streams", type=int, default=1024, help="resident streams at the start")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="device memory budget for admission")
+    ap.add_argument("--serve-churn", type=float, default=1.0, help="streams leaving (and joining) per second")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--host-frames", type=int, default=0, metavar="N",

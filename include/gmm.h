@@ -96,7 +96,8 @@ gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, in
  */
 gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out);
 
-/* Release a handle (synchronises the last stream it used first). NULL is a no-op. */
+/* Release a handle (synchronises the last stream it used first, then frees its state). NULL is a
+ * no-op. */
 gmm_status gmm_destroy(gmm_handle* h);
 
 /*
@@ -254,7 +255,7 @@ typedef struct {
 } gmm_exec_item;
 
 /*
- * Executor for the serving loop: three default-priority streams (copy-in, compute, copy-out)
+ * Executor for the serving loop: default-priority HIP streams (four copy-in, compute, copy-out)
  * pipeline consecutive ticks as in the paper's overlap of host transfers with device work
  * (Sec. IV, Fig. 4(a)); `ring` (1..64) bounds the ticks in flight. A completion thread records
  * each tick's completion time on the gmm_exec_now() clock.
@@ -269,6 +270,21 @@ gmm_status gmm_exec_set_tuning(gmm_exec* x, const gmm_batch_tuning* t);
 gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes);
 /* Release a stream's slot after its last tick has completed (waits for it). */
 gmm_status gmm_exec_detach(gmm_exec* x, gmm_handle* h);
+/* Device bytes of a stream created by gmm_exec_create_stream: its state (as gmm_state_bytes)
+ * rounded up to 256 bytes, then its frame slot. */
+gmm_status gmm_exec_stream_bytes(const gmm_config* cfg, size_t* bytes);
+/*
+ * Create and attach a stream whose state and frame slot live in caller-provided device memory
+ * `mem` (256-byte aligned, at least gmm_exec_stream_bytes). The state is initialised on the
+ * executor's compute stream, ordered before every later tick: no allocation and no host
+ * synchronisation, so streams can join a running server without stalling it. The caller keeps
+ * `mem` until gmm_exec_destroy_stream.
+ */
+gmm_status gmm_exec_create_stream(gmm_exec* x, const gmm_config* cfg, void* mem, size_t bytes,
+                                  gmm_handle** out);
+/* Detach and release a stream made by gmm_exec_create_stream once its last tick has completed
+ * (waits for that tick only); frees no device memory. */
+gmm_status gmm_exec_destroy_stream(gmm_exec* x, gmm_handle* h);
 /*
  * Advance the given streams (each at most once, none with a frame still in flight) by one frame
  * in one tick; returns at once with the tick's id (ids increase by 1 from 1). Blocks only when

@@ -38,6 +38,7 @@ EXPORTS = (
     "gmm_mask_confusion",
     "gmm_exec_create", "gmm_exec_destroy", "gmm_exec_set_tuning", "gmm_exec_attach", "gmm_exec_detach",
     "gmm_exec_launch", "gmm_exec_poll", "gmm_exec_drain", "gmm_exec_now",
+    "gmm_exec_stream_bytes", "gmm_exec_create_stream", "gmm_exec_destroy_stream",
 )
 
 
@@ -130,6 +131,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_int32)]),
         "gmm_exec_drain": (st, [H]),
         "gmm_exec_now": (ctypes.c_double, []),
+        "gmm_exec_stream_bytes": (st, [ctypes.POINTER(gmm_config), ctypes.POINTER(ctypes.c_size_t)]),
+        "gmm_exec_create_stream": (st, [H, ctypes.POINTER(gmm_config), vp, ctypes.c_size_t, ctypes.POINTER(H)]),
+        "gmm_exec_destroy_stream": (st, [H, H]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -354,3 +358,19 @@ def gmm_exec_drain(x):
 
 def gmm_exec_now() -> float:
     return load().gmm_exec_now()
+
+
+def gmm_exec_stream_bytes(cfg: gmm_config) -> int:
+    n = ctypes.c_size_t()
+    _check(load().gmm_exec_stream_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def gmm_exec_create_stream(x, cfg: gmm_config, mem_ptr: int, nbytes: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load().gmm_exec_create_stream(x, ctypes.byref(cfg), mem_ptr, nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def gmm_exec_destroy_stream(x, h):
+    _check(load().gmm_exec_destroy_stream(x, h))

@@ -172,15 +172,12 @@ gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, in
   return GMM_OK;
 }
 
-gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
-  if (!out) return fail(GMM_ERR_INVALID_ARG, "out is NULL");
+}  // extern "C"
+
+// Handle sizes, constants and pointers for `cfg` with its state at `mem` (not allocated here).
+gmm_status rgbd::new_handle(const gmm_config* cfg, gmm_handle** out) {
   gmm_status st = validate_config(cfg);
   if (st != GMM_OK) return st;
-  int ndev = 0;
-  hipError_t e = hipGetDeviceCount(&ndev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
-  if (cfg->device >= ndev) return fail(GMM_ERR_INVALID_ARG, "device ordinal out of range");
-
   gmm_handle* h = new (std::nothrow) gmm_handle();
   if (!h) return fail(GMM_ERR_OUT_OF_MEMORY, "host allocation of the handle failed");
   h->cfg = *cfg;
@@ -197,28 +194,56 @@ gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
   }
   h->kc = make_consts(*cfg, 0, false);
   h->kd = make_consts(*cfg, 1, cfg->hole_policy == GMM_HOLE_SKIP);
+  *out = h;
+  return GMM_OK;
+}
 
+void rgbd::place_state(gmm_handle* h, void* mem) {
+  h->mem = mem;
+  uint8_t* base = static_cast<uint8_t*>(mem);
+  h->st_rgb = has_rgb(h) ? base : nullptr;
+  h->st_depth = has_depth(h) ? base + h->rgb_bytes : nullptr;
+  h->fstate = has_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
+}
+
+hipError_t rgbd::init_state(gmm_handle* h, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (has_rgb(h)) e = launch_init(h->st_rgb, h->cfg.state_dtype, h->tiles64, h->cfg.M, 3, h->kc.var0, s);
+  if (e == hipSuccess && has_depth(h))
+    e = launch_init(h->st_depth, h->cfg.state_dtype, h->tiles64, h->cfg.M, 1, h->kd.var0, s);
+  if (e == hipSuccess && has_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, s);
+  return e;
+}
+
+size_t rgbd::state_bytes(const gmm_handle* h) { return h->rgb_bytes + h->depth_bytes + h->fuse_bytes; }
+
+extern "C" {
+
+gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
+  if (!out) return fail(GMM_ERR_INVALID_ARG, "out is NULL");
+  gmm_handle* h = nullptr;
+  gmm_status st = new_handle(cfg, &h);
+  if (st != GMM_OK) return st;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || cfg->device >= ndev) {
+    delete h;
+    return e != hipSuccess ? hip_fail(e, "hipGetDeviceCount") : fail(GMM_ERR_INVALID_ARG, "device ordinal out of range");
+  }
   DeviceGuard g(cfg->device);
   if (!g.ok()) {
     delete h;
     return fail(GMM_ERR_DEVICE, "cannot select the configured device");
   }
-  const size_t total = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
-  e = hipMalloc(&h->mem, total);
+  void* mem = nullptr;
+  e = hipMalloc(&mem, state_bytes(h));
   if (e != hipSuccess) {
     delete h;
     return fail(GMM_ERR_OUT_OF_MEMORY, std::string("hipMalloc of the state failed: ") + hipGetErrorString(e));
   }
-  uint8_t* base = static_cast<uint8_t*>(h->mem);
-  h->st_rgb = has_rgb(h) ? base : nullptr;
-  h->st_depth = has_depth(h) ? base + h->rgb_bytes : nullptr;
-  h->fstate = has_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
-
-  e = hipSuccess;
-  if (has_rgb(h)) e = launch_init(h->st_rgb, cfg->state_dtype, h->tiles64, cfg->M, 3, h->kc.var0, nullptr);
-  if (e == hipSuccess && has_depth(h))
-    e = launch_init(h->st_depth, cfg->state_dtype, h->tiles64, cfg->M, 1, h->kd.var0, nullptr);
-  if (e == hipSuccess && has_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, nullptr);
+  place_state(h, mem);
+  h->owns_mem = true;
+  e = init_state(h, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     (void)hipFree(h->mem);
@@ -232,7 +257,7 @@ gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out) {
 gmm_status gmm_destroy(gmm_handle* h) {
   if (!h) return GMM_OK;
   gmm_status st = GMM_OK;
-  {
+  if (h->owns_mem) {
     DeviceGuard g(h->cfg.device);
     hipError_t e = hipStreamSynchronize(h->last_stream);
     if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize in destroy");

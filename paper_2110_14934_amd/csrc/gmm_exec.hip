@@ -1,9 +1,10 @@
 // Serving executor: one call advances an arbitrary set of attached streams by one frame each,
 // taking their frames from (pinned) host memory and returning masks to host memory.
 //
-// Per tick, three HIP streams form the pipeline of the paper's Fig. 4(a): the frames of tick
-// N+1 are copied host->device while tick N is computed and the masks of tick N-1 are copied
-// back. Within a tick: host->device frame copies (copy-in stream) -> descriptor upload, a
+// Per tick, HIP streams form the pipeline of the paper's Fig. 4(a): the frames of tick N+1 are
+// copied host->device while tick N is computed and the masks of tick N-1 are copied back.
+// Within a tick: host->device frame copies (spread over four copy-in streams, so several DMA
+// engines share the host link) -> descriptor upload, a
 // device-built tile map and one persistent batched launch (compute stream) -> mask copies
 // device->host (copy-out stream). A ring of `ring` tick slots bounds the work in flight; a
 // completion thread waits on each tick's last event in order and records its completion time.
@@ -12,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -57,19 +59,29 @@ struct Attached {
   void* base = nullptr;           // the one device allocation holding the slots below
   uint8_t* d_rgb = nullptr;       // dense input slot (3 bytes per pixel)
   uint16_t* d_depth = nullptr;    // dense input slot (2 bytes per pixel)
-  uint64_t* d_masks = nullptr;    // fg_rgb | fg_depth | fused, one mask-size each
   size_t bytes = 0;
   int in_flight = 0;
 };
 
+constexpr int kCopyInStreams = 4;  // host->device copies spread over several DMA queues
+
 struct Slot {
-  hipEvent_t h2d_done = nullptr, compute_done = nullptr, done = nullptr;
+  hipEvent_t h2d_done[kCopyInStreams] = {};
+  hipEvent_t compute_done = nullptr, done = nullptr;
   FrameArgs* h_table = nullptr;   // pinned: n FrameArgs then n+1 uint32 tile starts
   size_t h_cap = 0;               // bytes
   void* d_table = nullptr;        // device copy of the same
   size_t d_cap = 0;
   uint32_t* d_tile_map = nullptr;
   size_t map_cap = 0;             // entries
+  uint64_t* d_masks = nullptr;    // every mask of the tick, back to back (device)
+  uint64_t* h_masks = nullptr;    // its pinned host copy
+  size_t mask_cap = 0;            // bytes
+  struct Out {
+    void* dst;
+    size_t off, bytes;
+  };
+  std::vector<Out> outs;          // where each mask goes once the tick has completed
   uint64_t tick = 0;
   bool busy = false;
   std::vector<gmm_handle*> handles;
@@ -82,7 +94,8 @@ struct gmm_exec {
   int M = -1, dtype = -1;
   int cu_count = 0;
   gmm_batch_tuning tuning{256, 1024, 8};
-  hipStream_t s_in = nullptr, s_compute = nullptr, s_out = nullptr;
+  hipStream_t s_in[kCopyInStreams] = {};
+  hipStream_t s_compute = nullptr, s_out = nullptr;
   std::vector<Slot> slots;
   std::map<const gmm_handle*, Attached> attached;
   uint64_t next_tick = 1;
@@ -108,6 +121,8 @@ static void completion_loop(gmm_exec* x) {
     }
     Slot& s = x->slots[slot];
     hipError_t e = hipEventSynchronize(s.done);
+    if (e == hipSuccess)
+      for (const auto& o : s.outs) std::memcpy(o.dst, reinterpret_cast<const char*>(s.h_masks) + o.off, o.bytes);
     const double t = now_s();
     std::lock_guard<std::mutex> lk(x->mu);
     if (e != hipSuccess && x->thread_error == hipSuccess) x->thread_error = e;
@@ -132,15 +147,20 @@ static void destroy_exec(gmm_exec* x) {
     x->worker.join();
   }
   for (auto& s : x->slots) {
-    if (s.h2d_done) (void)hipEventDestroy(s.h2d_done);
+    for (auto ev : s.h2d_done)
+      if (ev) (void)hipEventDestroy(ev);
     if (s.compute_done) (void)hipEventDestroy(s.compute_done);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.h_table) (void)hipHostFree(s.h_table);
     if (s.d_table) (void)hipFree(s.d_table);
     if (s.d_tile_map) (void)hipFree(s.d_tile_map);
+    if (s.d_masks) (void)hipFree(s.d_masks);
+    if (s.h_masks) (void)hipHostFree(s.h_masks);
   }
-  for (auto& kv : x->attached) (void)hipFree(kv.second.base);
-  if (x->s_in) (void)hipStreamDestroy(x->s_in);
+  for (auto& kv : x->attached)
+    if (kv.second.base) (void)hipFree(kv.second.base);
+  for (auto st : x->s_in)
+    if (st) (void)hipStreamDestroy(st);
   if (x->s_compute) (void)hipStreamDestroy(x->s_compute);
   if (x->s_out) (void)hipStreamDestroy(x->s_out);
   delete x;
@@ -167,12 +187,14 @@ gmm_status gmm_exec_create(int32_t device, int32_t ring, gmm_exec** out) {
   e = hipGetDeviceProperties(&prop, device);
   if (e == hipSuccess) x->cu_count = prop.multiProcessorCount;
   // default-priority, non-blocking streams
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->s_in, hipStreamNonBlocking);
+  for (auto& st : x->s_in)
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->s_compute, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->s_out, hipStreamNonBlocking);
   x->slots.resize(ring);
   for (auto& s : x->slots) {
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.h2d_done, hipEventDisableTiming);
+    for (auto& ev : s.h2d_done)
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.compute_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
   }
@@ -188,7 +210,7 @@ gmm_status gmm_exec_create(int32_t device, int32_t ring, gmm_exec** out) {
 gmm_status gmm_exec_destroy(gmm_exec* x) {
   if (!x) return GMM_OK;
   DeviceGuard g(x->device);
-  (void)hipStreamSynchronize(x->s_in);
+  for (auto st : x->s_in) (void)hipStreamSynchronize(st);
   (void)hipStreamSynchronize(x->s_compute);
   (void)hipStreamSynchronize(x->s_out);
   destroy_exec(x);
@@ -216,18 +238,16 @@ gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes) {
     return fail(GMM_ERR_INVALID_ARG, "all streams of an executor need the same M and state dtype");
   const size_t rgb = has_rgb(h) ? (static_cast<size_t>(h->npix) * 3 + 255) / 256 * 256 : 0;
   const size_t dep = has_depth(h) ? (static_cast<size_t>(h->npix) * 2 + 255) / 256 * 256 : 0;
-  const size_t masks = (mask_bytes(h) + 255) / 256 * 256 * 3;
   DeviceGuard g(x->device);
   void* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, rgb + dep + masks);
+  hipError_t e = hipMalloc(&mem, rgb + dep);
   if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "device allocation of the stream's frame slot failed");
   Attached a;
   uint8_t* base = static_cast<uint8_t*>(mem);
   a.base = mem;
   a.d_rgb = rgb ? base : nullptr;
   a.d_depth = dep ? reinterpret_cast<uint16_t*>(base + rgb) : nullptr;
-  a.d_masks = reinterpret_cast<uint64_t*>(base + rgb + dep);
-  a.bytes = rgb + dep + masks;
+  a.bytes = rgb + dep;
   x->attached[h] = a;
   x->M = h->cfg.M;
   x->dtype = h->cfg.state_dtype;
@@ -245,7 +265,7 @@ gmm_status gmm_exec_detach(gmm_exec* x, gmm_handle* h) {
   x->attached.erase(it);
   lk.unlock();
   DeviceGuard g(x->device);
-  (void)hipFree(base);
+  if (base) (void)hipFree(base);
   return GMM_OK;
 }
 
@@ -308,16 +328,41 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "device work-list allocation failed");
     s.d_cap = bytes * 2;
   }
+  // masks of the tick: one region per requested mask, 256-byte aligned, in one device arena
+  size_t mask_total = 0;
+  std::vector<size_t> moff(static_cast<size_t>(n) * 3, SIZE_MAX);
+  for (int32_t i = 0; i < n; ++i) {
+    const size_t mb = (mask_bytes(items[i].handle) + 255) / 256 * 256;
+    const gmm_handle* h = items[i].handle;
+    // the kernel writes a stream's masks whenever the modality is present; keep room for all
+    if (has_rgb(h)) moff[3 * i] = mask_total, mask_total += mb;
+    if (has_depth(h)) moff[3 * i + 1] = mask_total, mask_total += mb;
+    if (items[i].host_fused) moff[3 * i + 2] = mask_total, mask_total += mb;
+  }
+  if (mask_total > s.mask_cap) {
+    if (s.d_masks) (void)hipFree(s.d_masks);
+    if (s.h_masks) (void)hipHostFree(s.h_masks);
+    s.d_masks = nullptr;
+    s.h_masks = nullptr;
+    s.mask_cap = 0;
+    e = hipMalloc(reinterpret_cast<void**>(&s.d_masks), mask_total * 2);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s.h_masks), mask_total * 2, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "mask arena allocation failed");
+    s.mask_cap = mask_total * 2;
+  }
+  s.outs.clear();
   uint32_t* h_first = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s.h_table) + tab);
   uint64_t total_tiles = 0;
   for (int32_t i = 0; i < n; ++i) {
     const gmm_exec_item& it = items[i];
     gmm_handle* h = it.handle;
-    uint64_t* m = att[i].d_masks;
-    const size_t mw = (mask_bytes(h) + 255) / 256 * 256 / 8;
+    auto dm = [&](int k) { return moff[3 * i + k] == SIZE_MAX ? nullptr : s.d_masks + moff[3 * i + k] / 8; };
     s.h_table[i] = frame_args(h, att[i].d_rgb, 3 * static_cast<int64_t>(h->cfg.width), att[i].d_depth,
-                              2 * static_cast<int64_t>(h->cfg.width), has_rgb(h) ? m : nullptr,
-                              has_depth(h) ? m + mw : nullptr, it.host_fused ? m + 2 * mw : nullptr);
+                              2 * static_cast<int64_t>(h->cfg.width), dm(0), dm(1), dm(2));
+    const size_t mb = mask_bytes(h);
+    if (it.host_fg_rgb) s.outs.push_back({it.host_fg_rgb, moff[3 * i], mb});
+    if (it.host_fg_depth) s.outs.push_back({it.host_fg_depth, moff[3 * i + 1], mb});
+    if (it.host_fused) s.outs.push_back({it.host_fused, moff[3 * i + 2], mb});
     h_first[i] = static_cast<uint32_t>(total_tiles);
     total_tiles += (static_cast<uint64_t>(h->npix) + tile_px - 1) / tile_px;
   }
@@ -331,18 +376,28 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "device tile-map allocation failed");
     s.map_cap = total_tiles * 2;
   }
-  // copy-in: frames from host memory into the streams' device slots
+  // copy-in: frames from host memory into the streams' device slots, each frame on the least
+  // loaded of the copy-in streams (by bytes), so several DMA engines work at once
+  size_t queued[kCopyInStreams] = {};
   for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
     const gmm_handle* h = items[i].handle;
-    if (items[i].host_rgb)
-      e = hipMemcpyAsync(att[i].d_rgb, items[i].host_rgb, static_cast<size_t>(h->npix) * 3, hipMemcpyHostToDevice, x->s_in);
-    if (e == hipSuccess && items[i].host_depth)
+    int q = 0;
+    for (int c = 1; c < kCopyInStreams; ++c)
+      if (queued[c] < queued[q]) q = c;
+    if (items[i].host_rgb) {
+      e = hipMemcpyAsync(att[i].d_rgb, items[i].host_rgb, static_cast<size_t>(h->npix) * 3, hipMemcpyHostToDevice,
+                         x->s_in[q]);
+      queued[q] += static_cast<size_t>(h->npix) * 3;
+    }
+    if (e == hipSuccess && items[i].host_depth) {
       e = hipMemcpyAsync(att[i].d_depth, items[i].host_depth, static_cast<size_t>(h->npix) * 2, hipMemcpyHostToDevice,
-                         x->s_in);
+                         x->s_in[q]);
+      queued[q] += static_cast<size_t>(h->npix) * 2;
+    }
   }
-  if (e == hipSuccess) e = hipEventRecord(s.h2d_done, x->s_in);
+  for (int c = 0; c < kCopyInStreams && e == hipSuccess; ++c) e = hipEventRecord(s.h2d_done[c], x->s_in[c]);
   // compute: work list, tile map, one persistent launch over every item
-  if (e == hipSuccess) e = hipStreamWaitEvent(x->s_compute, s.h2d_done, 0);
+  for (int c = 0; c < kCopyInStreams && e == hipSuccess; ++c) e = hipStreamWaitEvent(x->s_compute, s.h2d_done[c], 0);
   if (e == hipSuccess) e = hipMemcpyAsync(s.d_table, s.h_table, bytes, hipMemcpyHostToDevice, x->s_compute);
   const FrameArgs* d_tab = static_cast<const FrameArgs*>(s.d_table);
   const uint32_t* d_first = reinterpret_cast<const uint32_t*>(static_cast<const char*>(s.d_table) + tab);
@@ -358,17 +413,10 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
                      static_cast<uint32_t>(total_tiles), tile_px, x->s_compute);
   }
   if (e == hipSuccess) e = hipEventRecord(s.compute_done, x->s_compute);
-  // copy-out: masks to host memory
+  // copy-out: the whole mask arena in one copy; the completion thread scatters it
   if (e == hipSuccess) e = hipStreamWaitEvent(x->s_out, s.compute_done, 0);
-  for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
-    const gmm_exec_item& it = items[i];
-    const size_t mb = mask_bytes(it.handle);
-    const size_t mw = (mb + 255) / 256 * 256 / 8;
-    uint64_t* m = att[i].d_masks;
-    if (it.host_fg_rgb) e = hipMemcpyAsync(it.host_fg_rgb, m, mb, hipMemcpyDeviceToHost, x->s_out);
-    if (e == hipSuccess && it.host_fg_depth) e = hipMemcpyAsync(it.host_fg_depth, m + mw, mb, hipMemcpyDeviceToHost, x->s_out);
-    if (e == hipSuccess && it.host_fused) e = hipMemcpyAsync(it.host_fused, m + 2 * mw, mb, hipMemcpyDeviceToHost, x->s_out);
-  }
+  if (e == hipSuccess && !s.outs.empty())
+    e = hipMemcpyAsync(s.h_masks, s.d_masks, mask_total, hipMemcpyDeviceToHost, x->s_out);
   if (e == hipSuccess) e = hipEventRecord(s.done, x->s_out);
   if (e != hipSuccess) return hip_fail(e, "executor tick");
   {
@@ -386,6 +434,71 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
   }
   x->cv.notify_all();
   if (tick_id) *tick_id = tick;
+  return GMM_OK;
+}
+
+gmm_status gmm_exec_stream_bytes(const gmm_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  gmm_handle* h = nullptr;
+  gmm_status st = new_handle(cfg, &h);
+  if (st != GMM_OK) return st;
+  const size_t n = static_cast<size_t>(h->npix);
+  const size_t slot = (has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0) + (has_depth(h) ? (n * 2 + 255) / 256 * 256 : 0);
+  *bytes = (state_bytes(h) + 255) / 256 * 256 + slot;
+  delete h;
+  return GMM_OK;
+}
+
+gmm_status gmm_exec_create_stream(gmm_exec* x, const gmm_config* cfg, void* mem, size_t bytes, gmm_handle** out) {
+  if (!x || !out || !mem) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(mem) % 256) return fail(GMM_ERR_INVALID_ARG, "mem must be 256-byte aligned");
+  if (cfg && cfg->device != x->device) return fail(GMM_ERR_INVALID_ARG, "configuration names another device");
+  size_t need = 0;
+  gmm_status st = gmm_exec_stream_bytes(cfg, &need);
+  if (st != GMM_OK) return st;
+  if (bytes < need) return fail(GMM_ERR_INVALID_ARG, "mem is smaller than gmm_exec_stream_bytes");
+  gmm_handle* h = nullptr;
+  st = new_handle(cfg, &h);
+  if (st != GMM_OK) return st;
+  std::lock_guard<std::mutex> lk(x->mu);
+  if (x->M >= 0 && (h->cfg.M != x->M || h->cfg.state_dtype != x->dtype)) {
+    delete h;
+    return fail(GMM_ERR_INVALID_ARG, "all streams of an executor need the same M and state dtype");
+  }
+  uint8_t* base = static_cast<uint8_t*>(mem);
+  place_state(h, base);
+  const size_t sb = (state_bytes(h) + 255) / 256 * 256;
+  const size_t n = static_cast<size_t>(h->npix);
+  Attached a;
+  a.base = nullptr;  // the caller's memory: never freed here
+  a.d_rgb = has_rgb(h) ? base + sb : nullptr;
+  a.d_depth = has_depth(h) ? reinterpret_cast<uint16_t*>(base + sb + (has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0)) : nullptr;
+  a.bytes = need;
+  DeviceGuard g(x->device);
+  // initialised on the compute stream: ordered before any tick that uses the stream
+  hipError_t e = init_state(h, x->s_compute);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "state initialisation");
+  }
+  h->last_stream = x->s_compute;
+  x->attached[h] = a;
+  x->M = h->cfg.M;
+  x->dtype = h->cfg.state_dtype;
+  *out = h;
+  return GMM_OK;
+}
+
+gmm_status gmm_exec_destroy_stream(gmm_exec* x, gmm_handle* h) {
+  if (!x || !h) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  if (h->owns_mem) return fail(GMM_ERR_INVALID_ARG, "not a stream created by gmm_exec_create_stream");
+  std::unique_lock<std::mutex> lk(x->mu);
+  auto it = x->attached.find(h);
+  if (it == x->attached.end()) return fail(GMM_ERR_INVALID_ARG, "handle not attached");
+  x->cv.wait(lk, [&] { return it->second.in_flight == 0; });  // its last frame has completed
+  x->attached.erase(it);
+  lk.unlock();
+  delete h;
   return GMM_OK;
 }
 

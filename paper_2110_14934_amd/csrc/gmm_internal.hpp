@@ -83,7 +83,8 @@ struct gmm_handle {  // the library's per-stream object (opaque in gmm.h)
   size_t rgb_bytes = 0;     // colour block
   size_t depth_bytes = 0;   // depth block
   size_t fuse_bytes = 0;    // List 1 state bytes (padded)
-  void* mem = nullptr;      // one device allocation: [colour][depth][fusion]
+  void* mem = nullptr;      // device state: [colour][depth][fusion]
+  bool owns_mem = false;    // allocated by gmm_create (else provided by the caller)
   void* st_rgb = nullptr;
   void* st_depth = nullptr;
   uint8_t* fstate = nullptr;
@@ -101,4 +102,11 @@ gmm_status check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch
                             int64_t depth_pitch, uint64_t* fg_rgb, uint64_t* fg_depth);
 FrameArgs frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch, const uint16_t* depth,
                      int64_t depth_pitch, uint64_t* fg_rgb, uint64_t* fg_depth, uint64_t* fused);
+// A validated handle with its sizes and constants, no device memory yet.
+gmm_status new_handle(const gmm_config* cfg, gmm_handle** out);
+// Point the handle's state at `mem` (state_bytes(h) bytes, 256-byte aligned).
+void place_state(gmm_handle* h, void* mem);
+// Enqueue the initial (all components empty) state on `s`.
+hipError_t init_state(gmm_handle* h, hipStream_t s);
+size_t state_bytes(const gmm_handle* h);
 }  // namespace rgbd

@@ -179,41 +179,82 @@ class Server:
                 self._release(st)
 
 
+class Arena:
+    """First-fit sub-allocator over one device reservation (offsets only; 256-byte granules).
+    Stream memory is carved from it at join and returned at leave, so the serving loop never
+    calls the device allocator while it runs."""
+
+    GRAIN = 256
+
+    def __init__(self, size: int):
+        self.size = size // self.GRAIN * self.GRAIN
+        self.free = [(0, self.size)]           # sorted, coalesced (offset, length)
+        self.used = {}                         # offset -> length
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        n = (nbytes + self.GRAIN - 1) // self.GRAIN * self.GRAIN
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + n, ln - n)
+                self.used[off] = n
+                return off
+        return None
+
+    def release(self, off: int):
+        n = self.used.pop(off)
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+    def free_bytes(self) -> int:
+        return sum(ln for _, ln in self.free)
+
+
 class NativeExecutor:
-    """The GPU executor: gmm_exec_* over handles created here."""
+    """The GPU executor (gmm_exec_*). Stream state and frame slots are carved from one device
+    reservation of `arena_bytes`, so joins and leaves allocate, free and synchronise nothing."""
 
     def __init__(self, device: int = 0, ring: int = 4, M: int = 5, state_dtype: str = "f16",
-                 tuning: Optional[Tuple[int, int, int]] = None, **params):
+                 tuning: Optional[Tuple[int, int, int]] = None, arena_bytes: int = 1 << 30, **params):
+        import torch
         self.device, self.M, self.dtype, self.params = device, M, state_dtype, params
         self.handle = _abi.gmm_exec_create(device, ring)
         if tuning:
             _abi.gmm_exec_set_tuning(self.handle, *tuning)
+        self.mem = torch.empty(arena_bytes, dtype=torch.uint8, device=torch.device("cuda", device))
+        self.base = self.mem.data_ptr()
+        self.arena = Arena(arena_bytes)
+        self.offsets = {}
+
+    def _cfg(self, width: int, height: int, modalities: int):
+        return _abi.gmm_config_default(width, height, modalities, self.M, state_dtype=_abi.DTYPES[self.dtype],
+                                       device=self.device, **self.params)
 
     def bytes_needed(self, width: int, height: int, modalities: int) -> int:
-        """Device bytes of a stream: tiled state + fusion bytes + frame slot + 3 masks."""
-        n = width * height
-        es = 4 if self.dtype == "f32" else 2
-        tiles = (n + 63) // 64
-        rgb, dep = bool(modalities & GMM_RGB), bool(modalities & GMM_DEPTH)
-        state = tiles * 64 * es * self.M * (5 * rgb + 3 * dep) + (((n + 255) // 256) * 256 if rgb and dep else 0)
-        up = lambda b: (b + 255) // 256 * 256
-        slot = (up(3 * n) if rgb else 0) + (up(2 * n) if dep else 0) + 3 * up((n + 63) // 64 * 8)
-        return state + slot
+        return _abi.gmm_exec_stream_bytes(self._cfg(width, height, modalities))
 
     def open_stream(self, width: int, height: int, modalities: int):
-        cfg = _abi.gmm_config_default(width, height, modalities, self.M, state_dtype=_abi.DTYPES[self.dtype],
-                                      device=self.device, **self.params)
-        h = _abi.gmm_create(cfg)
-        try:
-            slot = _abi.gmm_exec_attach(self.handle, h)
-        except Exception:
-            _abi.gmm_destroy(h)
-            raise
-        return h, _abi.gmm_state_bytes(h) + slot
+        cfg = self._cfg(width, height, modalities)
+        need = _abi.gmm_exec_stream_bytes(cfg)
+        off = self.arena.alloc(need)
+        if off is None:
+            raise MemoryError("executor arena exhausted")
+        h = _abi.gmm_exec_create_stream(self.handle, cfg, self.base + off, need)
+        self.offsets[h] = off
+        return h, need
 
     def close_stream(self, h):
-        _abi.gmm_exec_detach(self.handle, h)
-        _abi.gmm_destroy(h)
+        _abi.gmm_exec_destroy_stream(self.handle, h)
+        self.arena.release(self.offsets.pop(h))
 
     def launch(self, reqs) -> int:
         items = []
@@ -244,8 +285,12 @@ class NativeExecutor:
 
     def close(self):
         if self.handle is not None:
+            _abi.gmm_exec_drain(self.handle)
+            for h in list(self.offsets):
+                self.close_stream(h)
             _abi.gmm_exec_destroy(self.handle)
             self.handle = None
+            self.mem = None
 
 
 # ---- load generator --------------------------------------------------------------------------

@@ -88,12 +88,15 @@ def test_executor_ticks_bit_identical_to_plain_path():
 
 
 def test_memory_accounting_matches_allocation():
-    ex = NativeExecutor(ring=2, state_dtype="f16")
+    ex = NativeExecutor(ring=2, state_dtype="f16", arena_bytes=256 << 20)
     try:
+        free0 = ex.arena.free_bytes()
         for sp in SPECS + [StreamSpec(1920, 1080, rgb=True, depth=False), StreamSpec(512, 424, rgb=False)]:
             h, nbytes = ex.open_stream(sp.width, sp.height, mods(sp))
             assert nbytes == ex.bytes_needed(sp.width, sp.height, mods(sp)), sp
+            assert nbytes >= _abi.gmm_state_bytes(h) + sp.npix * (3 * sp.rgb + 2 * sp.depth)
             ex.close_stream(h)
+        assert ex.arena.free_bytes() == free0
     finally:
         ex.close()
 
@@ -106,8 +109,8 @@ def test_stream_alone_equals_stream_in_churning_mix():
     other_frames = [[(pinned(o.rgb(t)), pinned(o.depth(t))) for t in range(20)] for o in others]
 
     def run(mixed):
-        ex = NativeExecutor(ring=3, state_dtype="f16")
-        srv = Server(ex, 8 << 30, max_queue=64)
+        ex = NativeExecutor(ring=3, state_dtype="f16", arena_bytes=512 << 20)
+        srv = Server(ex, 512 << 20, max_queue=64)
         a = srv.join(sp.width, sp.height, GMM_RGB | GMM_DEPTH)
         live = []
         out = {}
@@ -161,8 +164,8 @@ def test_short_serving_run():
         pools[(k.width, k.height, k.modalities)] = [
             (pinned(st.rgb(t)) if k.modalities & GMM_RGB else None, pinned(st.depth(t)) if k.modalities & GMM_DEPTH else None)
             for t in range(4)]
-    ex = NativeExecutor(ring=4, state_dtype="f16")
-    srv = Server(ex, 4 << 30)
+    ex = NativeExecutor(ring=4, state_dtype="f16", arena_bytes=1 << 30)
+    srv = Server(ex, 1 << 30)
     try:
         rep = run_load(srv, pools, n_streams=48, duration_s=3.0, churn_per_s=2.0, mix=mix, warmup_s=0.5)
     finally:

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import MixParams, MixtureOracle
-from paper_2110_14934_amd.serve import FrameRequest, Server, run_load, StreamKind, GMM_RGB, GMM_DEPTH
+from paper_2110_14934_amd.serve import Arena, FrameRequest, Server, run_load, StreamKind, GMM_RGB, GMM_DEPTH
 
 
 class FakeExecutor:
@@ -213,3 +213,34 @@ def test_run_load_accounting_with_fake_clock():
     assert rep["p99_latency_ms"] < 40.0
     assert rep["stats"]["left"] >= 3 and rep["stats"]["joined"] >= 8 + 3
     assert math.isfinite(rep["pixel_updates_per_s"])
+
+
+def test_arena_first_fit_and_coalescing():
+    a = Arena(10 * 256 + 100)
+    assert a.size == 10 * 256
+    x = a.alloc(300)        # 2 granules
+    y = a.alloc(256)
+    z = a.alloc(1)
+    assert (x, y, z) == (0, 512, 768)
+    assert a.alloc(7 * 256) is None          # only 6 granules left
+    a.release(y)
+    assert a.alloc(256) == 512               # first fit reuses the hole
+    a.release(x)
+    a.release(512)
+    a.release(z)
+    assert a.free == [(0, 10 * 256)] and a.free_bytes() == 10 * 256
+    rng = np.random.default_rng(0)
+    live = {}
+    for _ in range(500):
+        if live and rng.random() < 0.5:
+            off = list(live)[rng.integers(len(live))]
+            a.release(off)
+            del live[off]
+        else:
+            n = int(rng.integers(1, 700))
+            off = a.alloc(n)
+            if off is not None:
+                for o, ln in live.items():   # no overlap with live blocks
+                    assert off + n <= o or o + ln <= off
+                live[off] = n
+    assert a.free_bytes() + sum(a.used.values()) == a.size
