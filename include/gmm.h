@@ -138,6 +138,15 @@ gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_
 /* Text of the last error on the calling thread; valid until that thread's next call. */
 const char* gmm_last_error(void);
 
+/*
+ * Measurement aid: when `wave_bytes` is a device array of ceil(width*height/64) uint64, every
+ * later launch on this handle (plain or batched) ADDS to entry i the bytes of mixture state that
+ * wave i (pixels 64i..64i+63) read and wrote. The traffic of a frame depends on the data: a wave
+ * whose pixels all match their top-ranked component and keep it moves only the weights and that
+ * component. NULL stops recording. The caller owns (and zeroes) the array.
+ */
+gmm_status gmm_set_traffic_record(gmm_handle* h, uint64_t* wave_bytes);
+
 /* Device bytes held by the handle's per-pixel state. */
 gmm_status gmm_state_bytes(const gmm_handle* h, size_t* device_bytes);
 

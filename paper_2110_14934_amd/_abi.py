@@ -39,6 +39,7 @@ EXPORTS = (
     "gmm_exec_create", "gmm_exec_destroy", "gmm_exec_set_tuning", "gmm_exec_attach", "gmm_exec_detach",
     "gmm_exec_launch", "gmm_exec_poll", "gmm_exec_drain", "gmm_exec_now",
     "gmm_exec_stream_bytes", "gmm_exec_create_stream", "gmm_exec_destroy_stream",
+    "gmm_set_traffic_record",
 )
 
 
@@ -134,6 +135,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "gmm_exec_stream_bytes": (st, [ctypes.POINTER(gmm_config), ctypes.POINTER(ctypes.c_size_t)]),
         "gmm_exec_create_stream": (st, [H, ctypes.POINTER(gmm_config), vp, ctypes.c_size_t, ctypes.POINTER(H)]),
         "gmm_exec_destroy_stream": (st, [H, H]),
+        "gmm_set_traffic_record": (st, [H, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -374,3 +376,8 @@ def gmm_exec_create_stream(x, cfg: gmm_config, mem_ptr: int, nbytes: int) -> int
 
 def gmm_exec_destroy_stream(x, h):
     _check(load().gmm_exec_destroy_stream(x, h))
+
+
+def gmm_set_traffic_record(h, wave_bytes):
+    """wave_bytes: device int64 tensor of ceil(npix/64) entries (accumulated into), or None."""
+    _check(load().gmm_set_traffic_record(h, _ptr(wave_bytes)))

@@ -268,6 +268,13 @@ gmm_status gmm_destroy(gmm_handle* h) {
   return st;
 }
 
+gmm_status gmm_set_traffic_record(gmm_handle* h, uint64_t* wave_bytes) {
+  if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
+  if (reinterpret_cast<uintptr_t>(wave_bytes) % 8) return fail(GMM_ERR_INVALID_ARG, "wave_bytes not 8-byte aligned");
+  h->wave_bytes = wave_bytes;
+  return GMM_OK;
+}
+
 gmm_status gmm_state_bytes(const gmm_handle* h, size_t* device_bytes) {
   if (!h || !device_bytes) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
   *device_bytes = h->rgb_bytes + h->depth_bytes + h->fuse_bytes;
@@ -331,6 +338,7 @@ FrameArgs rgbd::frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
   a.kc = h->kc;
   a.kd = h->kd;
   a.mode = (has_rgb(h) ? kModeRGB : 0) | (has_depth(h) ? kModeDepth : 0) | (fused ? kModeFuse : 0);
+  a.wave_bytes = h->wave_bytes;
   return a;
 }
 
@@ -415,10 +423,11 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     // tiled device layout -> canonical [param][rank][pixel]
     const uint32_t nv = static_cast<uint32_t>(P * M);
     for (size_t k = 0; k < P * M; ++k) {
+      const uint32_t v = value_index(static_cast<uint32_t>(k / M), static_cast<uint32_t>(k % M),
+                                     static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
       for (size_t i = 0; i < n; ++i) {
         const size_t at = off + (i / kWave) * tile_bytes +
-                          tile_value_offset(static_cast<uint32_t>(k), static_cast<uint32_t>(i % kWave), nv,
-                                            static_cast<uint32_t>(h->esize));
+                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), nv, static_cast<uint32_t>(h->esize));
         unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
       }
       o += n;
@@ -454,10 +463,11 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     // canonical [param][rank][pixel] -> tiled device layout
     const uint32_t nv = static_cast<uint32_t>(P * M);
     for (size_t k = 0; k < P * M; ++k) {
+      const uint32_t v = value_index(static_cast<uint32_t>(k / M), static_cast<uint32_t>(k % M),
+                                     static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
       for (size_t i = 0; i < n; ++i) {
         const size_t at = off + (i / kWave) * tile_bytes +
-                          tile_value_offset(static_cast<uint32_t>(k), static_cast<uint32_t>(i % kWave), nv,
-                                            static_cast<uint32_t>(h->esize));
+                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), nv, static_cast<uint32_t>(h->esize));
         pack_values(in + i, raw.data() + at, 1, h->cfg.state_dtype);
       }
       in += n;

@@ -65,9 +65,17 @@ struct Mix {
   float w[M];
 };
 
+// Order of a pixel's NV = (C+2)*M values: the M weights first, then rank by rank the variance
+// and the C means. The values a frame needs when the pixel matches its top-ranked component and
+// keeps its rank - every weight, rank 0, and rank 1's variance - are then a prefix.
+__host__ __device__ constexpr uint32_t value_index(uint32_t param, uint32_t rank, uint32_t M, uint32_t C) {
+  // param: 0..C-1 = mean channel, C = variance, C+1 = weight
+  return param == C + 1 ? rank : M + rank * (C + 1) + (param == C ? 0 : 1 + param);
+}
+
 // One modality's state block as a buffer resource, in a tiled layout. Pixels are grouped in
-// tiles of 64 (one wave); each pixel has NV = P*M values (plane order: mu channel 0..C-1, var,
-// w; each parameter M ranks). Inside a tile, values are stored in 16-byte chunks per lane: chunk
+// tiles of 64 (one wave); each pixel has NV values (in value_index order). Inside a tile, values
+// are stored in 16-byte chunks per lane: chunk
 // c holds values [c*VPC, (c+1)*VPC) of all 64 lanes as [lane][VPC] (VPC = 16/sizeof(value)), so
 // one wave instruction moves 1 KB of contiguous memory; the NV % VPC values left over are
 // stored as single rows [lane]. A wave's accesses to one modality fall in one contiguous region
@@ -142,81 +150,110 @@ template <> struct BufIO<bf16s> {
   }
 };
 
-// All NV values of pixel p (16-byte chunks, then single values).
-template <int NV, typename S>
+// Values [0, LIMIT) of pixel p: every 16-byte chunk and single value that starts below LIMIT
+// (whole chunks, so a little beyond LIMIT may come along). LIMIT = NV reads everything.
+template <int NV, int LIMIT, typename S>
 __device__ __forceinline__ void load_values(float (&v)[NV], const StateBlock& b, uint32_t p) {
   constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc, vpw = 4 / es;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_bytes;
 #pragma unroll
   for (uint32_t c = 0; c < nc; ++c) {
+    if (c * vpc >= static_cast<uint32_t>(LIMIT)) break;
     const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
 #pragma unroll
     for (uint32_t i = 0; i < vpc; ++i) v[c * vpc + i] = BufIO<S>::from_word(w[i / vpw], static_cast<int>(i % vpw));
   }
 #pragma unroll
-  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j) v[j] = BufIO<S>::ld(b, base + tile_value_offset(j, lane, NV, es));
+  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j)
+    if (j < static_cast<uint32_t>(LIMIT)) v[j] = BufIO<S>::ld(b, base + tile_value_offset(j, lane, NV, es));
 }
 
-template <int NV, typename S>
+template <int NV, int LIMIT, typename S>
 __device__ __forceinline__ void store_values(const float (&v)[NV], const StateBlock& b, uint32_t p) {
   constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc, vpw = 4 / es;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_bytes;
 #pragma unroll
   for (uint32_t c = 0; c < nc; ++c) {
+    if (c * vpc >= static_cast<uint32_t>(LIMIT)) break;
     u32x4 w;
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i) w[i] = BufIO<S>::word(&v[c * vpc + i * vpw]);
     __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
   }
 #pragma unroll
-  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j) BufIO<S>::st(b, base + tile_value_offset(j, lane, NV, es), v[j]);
+  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j)
+    if (j < static_cast<uint32_t>(LIMIT)) BufIO<S>::st(b, base + tile_value_offset(j, lane, NV, es), v[j]);
 }
 
-template <int M, int C, typename S>
+// Bytes of state one wave moves when it reads (or writes) values [0, LIMIT): whole chunks and
+// single rows that start below LIMIT, for all 64 lanes.
+template <int NV, int LIMIT, typename S>
+__host__ __device__ constexpr uint32_t prefix_bytes() {
+  constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc;
+  uint32_t chunks = 0, singles = 0;
+  for (uint32_t c = 0; c < nc; ++c)
+    if (c * vpc < static_cast<uint32_t>(LIMIT)) ++chunks;
+  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j)
+    if (j < static_cast<uint32_t>(LIMIT)) ++singles;
+  return chunks * 64u * kChunkBytes + singles * 64u * es;
+}
+
+// Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
+// it: all weights, rank 0 (variance, means) and the variance of rank 1.
+template <int M, int C>
+constexpr int kFastLoad = M > 1 ? M + (C + 1) + 1 : M + (C + 1);
+// ... and the values such a frame changes: all weights and rank 0.
+template <int M, int C>
+constexpr int kFastStore = M + (C + 1);
+
+template <int M, int C, typename S, int LIMIT = (C + 2) * M>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
   float v[(C + 2) * M];
-  load_values<(C + 2) * M, S>(v, b, p);
+#pragma unroll
+  for (int i = 0; i < (C + 2) * M; ++i) v[i] = 0.f;
+  load_values<(C + 2) * M, LIMIT, S>(v, b, p);
 #pragma unroll
   for (int r = 0; r < M; ++r) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) m.mu[c][r] = v[c * M + r];
-    m.var[r] = v[C * M + r];
-    m.w[r] = v[(C + 1) * M + r];
+    for (int c = 0; c < C; ++c) m.mu[c][r] = v[value_index(c, r, M, C)];
+    // a variance not read stays at 1: any use of it is discarded by the caller
+    m.var[r] = value_index(C, r, M, C) < static_cast<uint32_t>(LIMIT) ? v[value_index(C, r, M, C)] : 1.f;
+    m.w[r] = v[value_index(C + 1, r, M, C)];
   }
 }
 
-template <int M, int C, typename S>
+template <int M, int C, typename S, int LIMIT = (C + 2) * M>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
   float v[(C + 2) * M];
 #pragma unroll
   for (int r = 0; r < M; ++r) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) v[c * M + r] = m.mu[c][r];
-    v[C * M + r] = m.var[r];
-    v[(C + 1) * M + r] = m.w[r];
+    for (int c = 0; c < C; ++c) v[value_index(c, r, M, C)] = m.mu[c][r];
+    v[value_index(C, r, M, C)] = m.var[r];
+    v[value_index(C + 1, r, M, C)] = m.w[r];
   }
-  store_values<(C + 2) * M, S>(v, b, p);
-}
-
-template <typename T>
-__device__ __forceinline__ void cswap(bool s, T& a, T& b) {
-  const T ta = a, tb = b;
-  a = s ? tb : ta;
-  b = s ? ta : tb;
+  store_values<(C + 2) * M, LIMIT, S>(v, b, p);
 }
 
 // One frame of the mixture model for one pixel (Sec. III.A with the update rules of the
-// paper's reference [6]). Returns the foreground bit.
+// paper's reference [6]). Returns the foreground bit; `j_out` is the matched rank (M if none)
+// and `q_out` the rank the updated (or new) component ends up at.
 //   match    : first live rank, in stored (w/sigma descending) order, with |x-mu|^2 < k^2 var
 //   weights  : w <- (1-alpha) w + alpha [matched]
 //   matched  : mu <- (1-alpha) mu + alpha x ; var <- max(var_min, (1-alpha) var + alpha |x-mu_new|^2)
 //   no match : the last rank becomes (x, sigma0^2, w_init)
-//   then     : w <- w / sum(w); stable sort by w/sigma descending;
-//              B = min{b : w_0+...+w_{b-1} > T}; foreground = no match or new rank >= B
+//   then     : w <- w / sum(w); re-sort by w/sigma descending; B = min{b : w_0+...+w_{b-1} > T};
+//              foreground = no match or new rank >= B
+// Re-sort: the renormalisation scales every unchanged weight by the same factor, so the
+// unchanged components keep their order and only the updated one (t) can be out of place. It
+// walks up past neighbours with a strictly smaller key and down past neighbours with a strictly
+// larger key - the stable sort of the stored order. The walk stops at the first neighbour it may
+// not pass, so ranks beyond that neighbour are never consulted.
 template <int M, int C>
-__device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], const ModelConsts& k) {
+__device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], const ModelConsts& k, int& j_out,
+                                         int& q_out) {
   // match, in rank order
   int j = M;
 #pragma unroll
@@ -231,16 +268,17 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
     j = ((j == M) & hit) ? r : j;
   }
   const bool matched = j < M;
+  const int t = matched ? j : M - 1;
 
-  // weight decay; the matched component is gathered, updated once and scattered back
-  // (branch-free: every rank is a select, no per-rank divergent region)
-  float mj[C], vj = s.var[0];
+  // the changed component: gathered, updated once (branch-free selects over the ranks)
+  float mj[C], vj = s.var[0], wj = s.w[0];
 #pragma unroll
   for (int c = 0; c < C; ++c) mj[c] = s.mu[c][0];
 #pragma unroll
   for (int r = 1; r < M; ++r) {
     const bool isj = (r == j);
     vj = isj ? s.var[r] : vj;
+    wj = isj ? s.w[r] : wj;
 #pragma unroll
     for (int c = 0; c < C; ++c) mj[c] = isj ? s.mu[c][r] : mj[c];
   }
@@ -248,54 +286,71 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
-    const float t = x[c] - mj[c];
-    d2n = fmaf(t, t, d2n);
+    const float tt = x[c] - mj[c];
+    d2n = fmaf(tt, tt, d2n);
   }
   vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
+  wj = fmaf(k.oma, wj, k.alpha);
+  // no match: the least probable (last-ranked) component is replaced
+  float tmu[C], tvar, tw;
+#pragma unroll
+  for (int c = 0; c < C; ++c) tmu[c] = matched ? mj[c] : x[c];
+  tvar = matched ? vj : k.var0;
+  tw = matched ? wj : k.w_init;
+
+  // decay of the other weights, renormalisation of all
+  float w[M];
+  float S = 0.f;
 #pragma unroll
   for (int r = 0; r < M; ++r) {
-    const bool isj = (r == j);
-    s.w[r] = fmaf(k.oma, s.w[r], isj ? k.alpha : 0.f);
-    s.var[r] = isj ? vj : s.var[r];
-#pragma unroll
-    for (int c = 0; c < C; ++c) s.mu[c][r] = isj ? mj[c] : s.mu[c][r];
+    w[r] = (r == t) ? tw : k.oma * s.w[r];
+    S += w[r];
   }
-  // no match: the least probable (last-ranked) component is replaced
-  if (!matched) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) s.mu[c][M - 1] = x[c];
-    s.var[M - 1] = k.var0;
-    s.w[M - 1] = k.w_init;
-  }
-
-  // renormalise
-  float S = s.w[0];
-#pragma unroll
-  for (int r = 1; r < M; ++r) S += s.w[r];
   const float inv = 1.0f / S;
 #pragma unroll
-  for (int r = 0; r < M; ++r) s.w[r] *= inv;
+  for (int r = 0; r < M; ++r) w[r] *= inv;
+  tw = tw * inv;
 
-  // stable sort by w/sigma, descending (bubble network of adjacent compare-exchanges that swap
-  // only on a strictly larger key, hence stable); q follows the updated / new component
+  // re-sort: walk the changed component to its place
+  const float kt = tw * __builtin_amdgcn_rsqf(tvar);
   float key[M];
 #pragma unroll
-  for (int r = 0; r < M; ++r) key[r] = s.w[r] * __builtin_amdgcn_rsqf(s.var[r]);
-  int q = matched ? j : M - 1;
+  for (int r = 0; r < M; ++r) key[r] = w[r] * __builtin_amdgcn_rsqf(s.var[r]);
+  int down = 0, up = 0;
+  bool go_down = true, go_up = true;
 #pragma unroll
-  for (int i = 0; i < M - 1; ++i) {
+  for (int r = 1; r < M; ++r) {  // ranks below t, nearest first
+    const bool below = r > t;
+    go_down = go_down & (!below | (key[r] > kt));
+    down += (below & go_down) ? 1 : 0;
+  }
 #pragma unroll
-    for (int r = 0; r < M - 1 - i; ++r) {
-      const bool sw = key[r + 1] > key[r];
-      cswap(sw, key[r], key[r + 1]);
-      cswap(sw, s.w[r], s.w[r + 1]);
-      cswap(sw, s.var[r], s.var[r + 1]);
+  for (int r = M - 2; r >= 0; --r) {  // ranks above t, nearest first
+    const bool above = r < t;
+    go_up = go_up & (!above | (key[r] < kt));
+    up += (above & go_up) ? 1 : 0;
+  }
+  const int q = t + down - up;
+
+  // rank o takes: the changed component at q; above q the old rank o (or o+1 once past t);
+  // below q the old rank o (or o-1 once past t)
+  Mix<M, C> o;
 #pragma unroll
-      for (int c = 0; c < C; ++c) cswap(sw, s.mu[c][r], s.mu[c][r + 1]);
-      const int qs = (q == r) ? r + 1 : ((q == r + 1) ? r : q);
-      q = sw ? qs : q;
+  for (int r = 0; r < M; ++r) {
+    const int src = r < q ? (r < t ? r : r + 1) : (r > t ? r : r - 1);
+    const bool from_prev = src == r - 1, from_next = src == r + 1;
+    const int rp = r > 0 ? r - 1 : 0, rn = r < M - 1 ? r + 1 : M - 1;
+    float v = from_prev ? s.var[rp] : (from_next ? s.var[rn] : s.var[r]);
+    float ww = from_prev ? w[rp] : (from_next ? w[rn] : w[r]);
+    o.var[r] = (r == q) ? tvar : v;
+    o.w[r] = (r == q) ? tw : ww;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float mv = from_prev ? s.mu[c][rp] : (from_next ? s.mu[c][rn] : s.mu[c][r]);
+      o.mu[c][r] = (r == q) ? tmu[c] : mv;
     }
   }
+  s = o;
 
   // background set: the first B ranks whose cumulative weight exceeds T
   int B = M;
@@ -305,6 +360,8 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
     run += s.w[r];
     B = (B == M && run > k.T) ? r + 1 : B;
   }
+  j_out = j;
+  q_out = q;
   return !matched || q >= B;
 }
 

@@ -47,6 +47,40 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
   return static_cast<float>(row[xx]);
 }
 
+// One modality of pixel p, with lazy state traffic. First only the values a frame needs when
+// the pixel matches its rank-0 component and that component keeps its rank are read (all
+// weights, rank 0, rank 1's variance), and the step is run on them. If every active lane of the
+// wave took that path, only the weights and rank 0 are written back. Otherwise the wave reads
+// the whole state and runs the step again from the original values, then writes everything.
+// The step itself never depends on which path ran (the re-sort stops at the first neighbour it
+// may not pass, rank 1 here), so results are the same either way. `valid` lanes hold a pixel;
+// `active` lanes update it (a depth hole is valid but not active: it writes back what it read,
+// so every written row is whole). Returns the foreground bit; adds the state bytes this wave
+// moved to `wave_bytes`.
+template <int M, int C, typename S>
+__device__ __forceinline__ bool step_modality(const StateBlock& blk, uint32_t p, bool valid, bool active,
+                                              const float (&x)[C], const ModelConsts& k, uint32_t& wave_bytes) {
+  constexpr int NV = (C + 2) * M;
+  constexpr int LF = kFastLoad<M, C>;
+  constexpr int SF = kFastStore<M, C>;
+  Mix<M, C> m;
+  bool fg = false;
+  int j = 0, q = 0;
+  if (valid) load_mix<M, C, S, LF>(m, blk, p);
+  if (active) fg = mix_step<M, C>(m, x, k, j, q);
+  const bool slow = active && (j != 0 || q != 0);
+  if (__ballot(slow) == 0) {
+    if (valid) store_mix<M, C, S, SF>(m, blk, p);
+    wave_bytes += prefix_bytes<NV, LF, S>() + prefix_bytes<NV, SF, S>();
+  } else {
+    if (valid) load_mix<M, C, S, NV>(m, blk, p);
+    if (active) fg = mix_step<M, C>(m, x, k, j, q);
+    if (valid) store_mix<M, C, S, NV>(m, blk, p);
+    wave_bytes += 2 * prefix_bytes<NV, NV, S>();
+  }
+  return fg;
+}
+
 // Pixel p of stream `a` (p may lie past the end: such lanes only take part in the ballots).
 // `mode` must be uniform over the wave.
 template <int M, typename S>
@@ -55,31 +89,21 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   const uint32_t wave_base = p - lane;
   const bool valid = p < a.npix;
   bool fgc = false, fgd = false;
+  uint32_t wave_bytes = 0;
   if ((mode & kModeRGB) != 0) {
     float x[3];
     load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);
-    if (valid) {
-      Mix<M, 3> m;
-      const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
-      load_mix<M, 3, S>(m, blk, p);
-      fgc = mix_step<M, 3>(m, x, a.kc);
-      store_mix<M, 3, S>(m, blk, p);
-    }
+    const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
+    fgc = step_modality<M, 3, S>(blk, p, valid, valid, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fgc);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
   if ((mode & kModeDepth) != 0) {
-    if (valid) {
-      const float xd = load_depth_pixel(a, p);
-      if (!(a.kd.hole_skip && xd == 0.f)) {
-        Mix<M, 1> m;
-        const StateBlock blk = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
-        load_mix<M, 1, S>(m, blk, p);
-        const float x1[1] = {xd};
-        fgd = mix_step<M, 1>(m, x1, a.kd);
-        store_mix<M, 1, S>(m, blk, p);
-      }
-    }
+    const float xd = valid ? load_depth_pixel(a, p) : 0.f;
+    const bool active = valid && !(a.kd.hole_skip && xd == 0.f);
+    const StateBlock blk = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
+    const float x1[1] = {xd};
+    fgd = step_modality<M, 1, S>(blk, p, valid, active, x1, a.kd, wave_bytes);
     const uint64_t bits = __ballot(fgd);
     if (lane == 0 && valid) a.fg_depth[wave_base >> 6] = bits;
   }
@@ -93,6 +117,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     const uint64_t bits = __ballot(fgf);
     if (lane == 0 && valid) a.fused[wave_base >> 6] = bits;
   }
+  // one wave owns each entry, and launches on a handle are ordered: a plain add is exact
+  if (a.wave_bytes != nullptr && lane == 0 && valid) a.wave_bytes[wave_base >> 6] += wave_bytes;
 }
 
 }  // namespace rgbd

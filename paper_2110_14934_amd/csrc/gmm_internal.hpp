@@ -33,6 +33,7 @@ struct FrameArgs {
   ModelConsts kd;          // depth constants
   int32_t mode;            // kModeRGB | kModeDepth | kModeFuse bits of this stream
   int32_t pad_;
+  uint64_t* wave_bytes;    // optional: per-wave running total of state bytes moved (measurement)
 };
 
 enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4 };
@@ -85,6 +86,7 @@ struct gmm_handle {  // the library's per-stream object (opaque in gmm.h)
   size_t fuse_bytes = 0;    // List 1 state bytes (padded)
   void* mem = nullptr;      // device state: [colour][depth][fusion]
   bool owns_mem = false;    // allocated by gmm_create (else provided by the caller)
+  uint64_t* wave_bytes = nullptr;  // optional per-wave traffic record (gmm_set_traffic_record)
   void* st_rgb = nullptr;
   void* st_depth = nullptr;
   uint8_t* fstate = nullptr;

@@ -55,8 +55,9 @@ __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, i
   const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
   const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
   const int64_t byte = tile * nv * kWave * static_cast<int64_t>(sizeof(S)) + tile_value_offset(v, lane, nv, sizeof(S));
-  const uint32_t param = v / static_cast<uint32_t>(M);
-  *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(param == static_cast<uint32_t>(C) ? var0 : 0.f);
+  // value order: M weights, then per rank (variance, C means)
+  const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(is_var ? var0 : 0.f);
 }
 
 __global__ void __launch_bounds__(kBlock) fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {

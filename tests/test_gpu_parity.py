@@ -406,3 +406,29 @@ def test_error_paths_on_device():
         assert seg.state_bytes() == 5 * 3 * 256 * 4
     finally:
         seg.close()
+
+
+def test_traffic_record_counts_fast_and_full_waves():
+    """Frame 0 matches nothing (every wave reads and writes the whole state: 2 x 40 values x 64
+    lanes x 4 B = 20480 B per wave); the same frame again matches rank 0 everywhere and keeps the
+    order, so every wave moves only the weights and rank 0 (+ rank 1's variance on the read side):
+    colour 3 + 3 chunks, depth 2 + 2 chunks of 1 KB = 10240 B."""
+    spec = StreamSpec(160, 120, n_boxes=1, box_min=20, box_max=20, hole_p=0.05, seed=61)
+    st = Stream(spec)
+    seg = Segmenter(160, 120, GMM_RGB | GMM_DEPTH, 5)
+    rec = torch.zeros(spec.npix // 64, dtype=torch.int64, device=DEV)
+    try:
+        _abi.gmm_set_traffic_record(seg.handle, rec)
+        rgb, depth = st.rgb(0, device=DEV), st.depth(0, device=DEV)
+        seg.apply_fused(rgb, depth)
+        torch.cuda.synchronize()
+        assert torch.all(rec == 20480)
+        seg.apply_fused(rgb, depth)
+        torch.cuda.synchronize()
+        assert torch.all(rec == 20480 + 10240)
+        _abi.gmm_set_traffic_record(seg.handle, None)
+        seg.apply_fused(rgb, depth)
+        torch.cuda.synchronize()
+        assert torch.all(rec == 30720)
+    finally:
+        seg.close()
