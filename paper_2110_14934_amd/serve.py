@@ -154,7 +154,14 @@ class Server:
             req = st.queue.popleft()
             st.in_flight = req
             reqs.append((st, req))
-        tick = self.x.launch(reqs)
+        try:
+            tick = self.x.launch(reqs)
+        except Exception:
+            # nothing was enqueued: the frames go back to the head of their queues
+            for st, req in reqs:
+                st.in_flight = None
+                st.queue.appendleft(req)
+            raise
         for _, req in reqs:
             req.tick = tick
         self.ticks[tick] = [r for _, r in reqs]

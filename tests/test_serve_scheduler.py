@@ -244,3 +244,30 @@ def test_arena_first_fit_and_coalescing():
                     assert off + n <= o or o + ln <= off
                 live[off] = n
     assert a.free_bytes() + sum(a.used.values()) == a.size
+
+
+def test_failed_launch_leaves_the_server_consistent():
+    class Failing(FakeExecutor):
+        fail_next = True
+
+        def launch(self, reqs):
+            if self.fail_next:
+                self.fail_next = False
+                raise RuntimeError("device error")
+            return super().launch(reqs)
+
+    x = Failing()
+    x._done = []
+    srv = Server(x, 10 ** 6)
+    a, b = srv.join(2, 2, GMM_DEPTH), srv.join(2, 2, GMM_DEPTH)
+    srv.submit(_req(a, 0))
+    srv.submit(_req(a, 1))
+    srv.submit(_req(b, 0))
+    with pytest.raises(RuntimeError):
+        srv.step()
+    assert srv.in_flight() == 0
+    assert [r.seq for r in srv.streams[a].queue] == [0, 1] and [r.seq for r in srv.streams[b].queue] == [0]
+    srv.step()                                      # the retry launches the same frames, in order
+    x.complete_all()
+    done = srv.step()
+    assert sorted((r.stream_id, r.seq) for r in done) == [(a, 0), (b, 0)]
