@@ -7,6 +7,10 @@ Default workload: one 640x480 RGB-D stream, M=5, fp32 state, the 300-frame synth
 before timing starts. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+The ablation variants run on the same clip: --rho density (the density rate of the mean and
+variance updates) and --variant augmented (one four-channel R, G, B, depth-byte mixture per
+pixel instead of two mixtures and List 1; one mixture update per pixel).
 """
 from __future__ import annotations
 
@@ -66,32 +70,41 @@ def io_bytes_per_frame(npix: int, rgb: bool = True, depth: bool = True, fused: b
     return b
 
 
-def cpu_baseline(wl, seconds: float):
+def cpu_baseline(wl, seconds: float, rho: str = "alpha", augmented: bool = False):
     """The FP64 oracle on the host: whole frames of the same stream until `seconds` elapse."""
     import numpy as np
-    from oracle import MixParams, MixtureOracle, FusionOracle
+    from oracle import MixParams, MixtureOracle, FusionOracle, AugmentedOracle
     from paper_2110_14934_amd.synth import Stream
     spec, mix = wl.streams[0], wl.mix
     st = Stream(spec)
     n = spec.npix
-    col = MixtureOracle(MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_rgb, mix.var_min_rgb, mix.w_init), 3, n)
-    dep = MixtureOracle(MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_depth, mix.var_min_depth,
-                                  mix.w_init, hole_skip=True), 1, n)
-    fus = FusionOracle(n)
+    pc = MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_rgb, mix.var_min_rgb, mix.w_init, rho=rho)
+    if augmented:
+        aug = AugmentedOracle(MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_rgb, mix.var_min_rgb, mix.w_init,
+                                        hole_skip=True, rho=rho), n)
+    else:
+        col = MixtureOracle(pc, 3, n)
+        dep = MixtureOracle(MixParams(mix.M, mix.alpha, mix.k, mix.T, mix.sigma0_depth, mix.var_min_depth,
+                                      mix.w_init, hole_skip=True, rho=rho), 1, n)
+        fus = FusionOracle(n)
     elapsed, frames = 0.0, 0
     while elapsed < seconds and frames < wl.frames:
         rgb = st.rgb(frames).reshape(-1, 3).numpy()
         dep_f = st.depth(frames).reshape(-1).numpy()
         t0 = time.perf_counter()
-        ic = col.step(rgb)
-        idd = dep.step(dep_f)
-        fus.step(ic.fg, idd.fg)
+        if augmented:
+            aug.step(rgb, dep_f)
+        else:
+            ic = col.step(rgb)
+            idd = dep.step(dep_f)
+            fus.step(ic.fg, idd.fg)
         elapsed += time.perf_counter() - t0
         frames += 1
-    pu = 2 * n * frames
+    pu = (1 if augmented else 2) * n * frames
+    what = "four-channel mixture" if augmented else "colour+depth+fusion"
     return {"value": pu / elapsed, "unit": "pixel-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"frames 0-{frames - 1} of the {spec.width}x{spec.height} RGB-D stream, all {n} pixels, "
-                      f"colour+depth+fusion, float64 NumPy on one host core ({elapsed:.1f} s)",
+                      f"{what}, rho={rho}, float64 NumPy on one host core ({elapsed:.1f} s)",
             "host_cpus": os.cpu_count()}
 
 
@@ -281,6 +294,10 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-streams", type=int, default=1024, help="resident streams at the start")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="device memory budget for admission")
     ap.add_argument("--serve-churn", type=float, default=1.0, help="streams leaving (and joining) per second")
+    ap.add_argument("--rho", choices=("alpha", "density"), default="alpha",
+                    help="rate of the mean and variance updates (plain workload)")
+    ap.add_argument("--variant", choices=("separate", "augmented"), default="separate",
+                    help="separate colour and depth models + List 1 (the method), or one four-channel model")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--host-frames", type=int, default=0, metavar="N",
@@ -332,7 +349,16 @@ def main(argv=None) -> int:
     print(f"[bench] {F} frames of {spec.width}x{spec.height} resident on {torch.cuda.get_device_name(0)}",
           file=sys.stderr, flush=True)
 
-    seg = Segmenter(spec.width, spec.height, GMM_RGB | GMM_DEPTH, mix.M, state_dtype=wl.state_dtype)
+    augmented = args.variant == "augmented"
+    seg = Segmenter(spec.width, spec.height, GMM_RGB | GMM_DEPTH, mix.M, state_dtype=wl.state_dtype,
+                    rho=args.rho, augmented=augmented)
+
+    def step(rgb, dep, s):
+        if augmented:
+            seg.apply_augmented(rgb, dep, s)
+        else:
+            seg.apply_fused(rgb, dep, s)
+
     # per-wave record of the state bytes each launch moves (the traffic depends on the data)
     record = torch.zeros((n + 63) // 64, dtype=torch.int64, device=dev)
     _abi.gmm_set_traffic_record(seg.handle, record)
@@ -341,7 +367,7 @@ def main(argv=None) -> int:
 
     with torch.cuda.stream(stream):
         for t in range(W):
-            seg.apply_fused(rgbs[t % F], deps[t % F], stream)
+            step(rgbs[t % F], deps[t % F], stream)
     stream.synchronize()
 
     graph = None
@@ -351,7 +377,7 @@ def main(argv=None) -> int:
         with torch.cuda.graph(graph, stream=stream):
             for i in range(F):
                 t = (W + i) % F
-                seg.apply_fused(rgbs[t], deps[t], torch.cuda.current_stream())
+                step(rgbs[t], deps[t], torch.cuda.current_stream())
         # capture does not execute: restore the state the warm-up left
         torch.cuda.synchronize()
 
@@ -381,7 +407,7 @@ def main(argv=None) -> int:
         with torch.cuda.stream(stream):
             for i in range(K):
                 t = (W + i) % F
-                seg.apply_fused(rgbs[t], deps[t], stream)
+                step(rgbs[t], deps[t], stream)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
@@ -407,18 +433,19 @@ def main(argv=None) -> int:
         copy_gbs = 2 * half / (c0.elapsed_time(c1) / 200 / 1e3) / 1e9
         del src, dst
 
-    pu_step = 2 * n
+    pu_step = (1 if augmented else 2) * n
     value = pu_step * K / (ms_total / 1e3)
     idx = [(W + i) % F for i in range(K)]
     mean_holes = float(holes[idx].mean())
     esize = 4 if wl.state_dtype == "f32" else 2
     sorted_bytes = bytes_per_frame(n, mean_holes, mix.M, esize)
     state_bytes = float(record.sum().item()) / K
-    alg_bytes = state_bytes + io_bytes_per_frame(n)
+    # augmented: colour and depth inputs, one mask, no fusion state
+    alg_bytes = state_bytes + (n * (3 + 2 + 1 / 8) if augmented else io_bytes_per_frame(n))
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
 
     traffic = None
-    if os.path.exists(PROFILE_TRAFFIC):
+    if os.path.exists(PROFILE_TRAFFIC) and not augmented and args.rho == "alpha":
         rec = json.load(open(PROFILE_TRAFFIC))
         if rec.get("kernel_source_digest") == kernel_source_digest():
             traffic = rec.get("hbm_bytes_per_launch")
@@ -437,13 +464,14 @@ def main(argv=None) -> int:
         "dtype": "f32",
         "data": "synthetic (seeded Kinect-shaped RGB-D stream; the paper's captures are not available)",
         "config": {"workload": args.workload, "streams": 1, "width": spec.width, "height": spec.height,
-                   "M": mix.M, "modalities": "rgb+depth+fusion", "state_dtype": wl.state_dtype,
-                   "clip_frames": F, "launch": args.mode},
+                   "M": mix.M, "modalities": "rgb+depth (one 4-channel mixture)" if augmented else "rgb+depth+fusion",
+                   "state_dtype": wl.state_dtype, "clip_frames": F, "launch": args.mode, "rho": args.rho,
+                   "variant": args.variant},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "rgbd::frame_kernel<5, float, 7>",
+                     "kernel": f"rgbd::frame_kernel<5, float, {8 if augmented else 7}>",
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "full_rewrite_bytes_per_launch": sorted_bytes,
+                     "full_rewrite_bytes_per_launch": None if augmented else sorted_bytes,
                      "avg_launch_us": ms_step * 1e3,
                      "device_copy_same_bytes_gbs": copy_gbs},
         "frames_per_s": 1e3 / ms_step,
@@ -451,7 +479,7 @@ def main(argv=None) -> int:
                           "note": "30 fps VGA colour+depth end to end incl. transfers, unnamed GPU (Sec. V.B)"},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.rho, augmented)
     seg.close()
     print(json.dumps(out), flush=True)
     return 0

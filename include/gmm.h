@@ -53,6 +53,18 @@ typedef enum {
 enum { GMM_RGB = 1, GMM_DEPTH = 2 };
 /* storage type of the per-pixel mixture state (arithmetic is always fp32) */
 enum { GMM_F32 = 0, GMM_F16 = 1, GMM_BF16 = 2 };
+/* which model the handle runs */
+enum { GMM_SEPARATE = 0,       /* the method: colour and depth mixtures kept apart (Sec. III.B),
+                                  their masks fused by List 1 (Sec. III.C)                   */
+       GMM_AUGMENTED = 1 };    /* the alternative Sec. III.B describes and rejects: one mixture
+                                  over four channels (R, G, B, D8), D8 = min(255, depth >> 4),
+                                  the depth in 16 mm steps as a fourth intensity byte; one
+                                  isotropic variance per component, colour sigma0 / var_min */
+/* rate rho of the mean and variance updates */
+enum { GMM_RHO_ALPHA = 0,      /* rho = alpha                                               */
+       GMM_RHO_DENSITY = 1 };  /* rho = alpha * N(x | mu, var I): the matched component's
+                                  isotropic Gaussian density at x before the update (the rate
+                                  of the paper's reference [6], Stauffer and Grimson)         */
 /* depth value 0 ("no reading" on a Kinect-class sensor) */
 enum { GMM_HOLE_SKIP = 0,      /* state untouched, pixel classified background             */
        GMM_HOLE_AS_VALUE = 1 };/* 0 is treated as an ordinary distance                     */
@@ -76,6 +88,8 @@ typedef struct {
   int32_t hole_policy;     /* GMM_HOLE_SKIP or GMM_HOLE_AS_VALUE                            */
   int32_t state_dtype;     /* GMM_F32, GMM_F16 or GMM_BF16                                  */
   int32_t device;          /* HIP device ordinal                                            */
+  int32_t variant;         /* GMM_SEPARATE or GMM_AUGMENTED (needs both modalities)         */
+  int32_t rho_mode;        /* GMM_RHO_ALPHA or GMM_RHO_DENSITY                              */
 } gmm_config;
 
 typedef struct gmm_handle gmm_handle;
@@ -83,7 +97,8 @@ typedef struct gmm_handle gmm_handle;
 /*
  * Fill `cfg` with this library's defaults for a width x height stream: alpha = 0.01, k = 2.5,
  * T = 0.7, sigma0 = {30, 50}, var_min = {(0.1 sigma0)^2} = {9, 25}, w_init = alpha,
- * GMM_HOLE_SKIP, GMM_F32, device 0. The caller may then change any field.
+ * GMM_HOLE_SKIP, GMM_F32, device 0, GMM_SEPARATE, GMM_RHO_ALPHA. The caller may then change
+ * any field.
  */
 gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, int32_t modalities,
                               int32_t M);
@@ -102,7 +117,7 @@ gmm_status gmm_destroy(gmm_handle* h);
 
 /*
  * Advance the model one frame and classify it (Sec. III.A, per modality; Sec. III.B keeps the
- * two modalities separate).
+ * two modalities separate). GMM_ERR_STATE on a GMM_AUGMENTED handle.
  *   rgb        device HWC interleaved uint8 R,G,B; row y starts at rgb + y*rgb_pitch_bytes
  *              (pitch >= 3*width). NULL exactly when the handle has no colour modality.
  *   depth      device uint16 millimetres, row pitch depth_pitch_bytes (even, >= 2*width);
@@ -135,6 +150,17 @@ gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_
                                  uint64_t* fg_rgb, uint64_t* fg_depth, uint64_t* fused,
                                  void* stream);
 
+/*
+ * The four-channel variant of Sec. III.B (a GMM_AUGMENTED handle, else GMM_ERR_STATE): one
+ * mixture step per pixel on x = (R, G, B, min(255, depth >> 4)) and its foreground mask `fg`.
+ * rgb, depth and their pitches as in gmm_apply_frame; all three pointers are required. With
+ * GMM_HOLE_SKIP a depth of 0 leaves the pixel's state untouched and classifies it background.
+ * A single-stream path for comparisons: batches and the serving executor reject such handles.
+ */
+gmm_status gmm_apply_frame_augmented(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_bytes,
+                                     const uint16_t* depth, int64_t depth_pitch_bytes, uint64_t* fg,
+                                     void* stream);
+
 /* Text of the last error on the calling thread; valid until that thread's next call. */
 const char* gmm_last_error(void);
 
@@ -156,7 +182,8 @@ gmm_status gmm_state_bytes(const gmm_handle* h, size_t* device_bytes);
  * colour block: 5 x M x npix  parameters (muR, muG, muB, var, w), each rank-major;
  * depth block:  3 x M x npix  parameters (mu, var, w);
  * I and cpt:    npix each, present only for two-modality handles.
- * Blocks of absent modalities are omitted. Components appear in rank order (w/sigma
+ * Blocks of absent modalities are omitted. A GMM_AUGMENTED handle has one block,
+ * 6 x M x npix parameters (muR, muG, muB, muD8, var, w), and no I, cpt. Components appear in rank order (w/sigma
  * descending); an empty component has w = 0.
  */
 gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles);
@@ -203,6 +230,7 @@ typedef struct {
  * `n_slots` descriptor slots (1..4096) hold prepared frame-sets, so launches can be captured in
  * a hipGraph and replayed. The handles must outlive the batch and must not be used by other
  * calls while batch work on them is in flight. Default tuning: {256, 1024, 8}.
+ * GMM_ERR_UNSUPPORTED for a GMM_AUGMENTED handle.
  */
 gmm_status gmm_batch_create(gmm_handle* const* handles, int32_t n, int32_t n_slots, gmm_batch** out);
 
@@ -275,7 +303,8 @@ gmm_status gmm_exec_destroy(gmm_exec* x);
 /* Launch shape of the batched kernel (same meaning and limits as gmm_batch_tuning). */
 gmm_status gmm_exec_set_tuning(gmm_exec* x, const gmm_batch_tuning* t);
 /* Give a stream a device frame slot and device masks (all streams of an executor share M and
- * the state dtype). Reports the device bytes this adds, for memory admission. */
+ * the state dtype). Reports the device bytes this adds, for memory admission.
+ * GMM_ERR_UNSUPPORTED for a GMM_AUGMENTED handle (also in the two calls below). */
 gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes);
 /* Release a stream's slot after its last tick has completed (waits for it). */
 gmm_status gmm_exec_detach(gmm_exec* x, gmm_handle* h);

@@ -32,6 +32,11 @@ Readings taken where the paper is silent or garbled (each pinned by a test where
   * the match test is strict (a distance exactly k sigma does not match);
   * depth 0 is a missing reading (optional, the hole policy).
 
+Variant (an ablation, ``MixParams.rho = "density"``): the mean and variance rate is
+Stauffer and Grimson's rho = alpha * eta(x | mu_j, var_j I), the C-variate isotropic Gaussian
+density of x under the matched component before its update,
+eta = (2 pi var_j)^(-C/2) exp(-||x - mu_j||^2 / (2 var_j)).
+
 Besides the result, every step records how close each discrete decision came to flipping
 (``StepInfo``), so a finite-precision implementation can be compared pixel by pixel with
 its legitimately ambiguous decisions excused.
@@ -54,6 +59,7 @@ class MixParams:
     var_min: float
     w_init: float
     hole_skip: bool = False   # depth only: value 0 means "no reading"
+    rho: str = "alpha"        # "alpha" or "density" (rate of the mean and variance updates)
 
 
 @dataclass
@@ -121,13 +127,17 @@ class MixtureOracle:
         self.w = np.array(w, dtype=np.float64).reshape(self.p.M, self.n)
 
     # -- one frame --------------------------------------------------------------------------
-    def step(self, x) -> StepInfo:
+    def step(self, x, hole=None) -> StepInfo:
+        """Advance one frame. ``hole`` (bool (n,)) marks pixels to skip; by default, with the
+        hole policy on, a one-channel value of 0."""
         p, M, C, n = self.p, self.p.M, self.C, self.n
         a = float(p.alpha)
         x = np.asarray(x, dtype=np.float64).reshape(n, C).T          # (C, n)
         mu, var, w = self.mu, self.var, self.w
 
-        if p.hole_skip and C == 1:
+        if hole is not None:
+            hole = np.asarray(hole, dtype=bool).reshape(n)
+        elif p.hole_skip and C == 1:
             hole = x[0] == 0.0
         else:
             hole = np.zeros(n, dtype=bool)
@@ -136,9 +146,11 @@ class MixtureOracle:
         k2 = p.k * p.k
         j = np.full(n, -1, dtype=np.int64)
         match_margin = np.full(n, np.inf)
+        d2_all = np.zeros((M, n))
         for r in range(M):
             live = w[r] > 0.0
             d2 = ((x - mu[r]) ** 2).sum(axis=0)
+            d2_all[r] = d2
             hit = live & (d2 < k2 * var[r])
             tested = live & (j < 0)
             sd = np.sqrt(var[r])
@@ -151,10 +163,19 @@ class MixtureOracle:
         onehot = np.arange(M)[:, None] == j[None, :]                 # (M, n)
         w_new = (1.0 - a) * w + a * onehot
 
-        # 4. matched component: mean first, then variance about the new mean
-        mu_upd = (1.0 - a) * mu + a * x[None, :, :]
+        # 4. matched component: mean first, then variance about the new mean, at rate rho
+        if p.rho == "alpha":
+            rho = np.full(n, a)
+        elif p.rho == "density":
+            jj = np.maximum(j, 0)[None, :]
+            d2j = np.take_along_axis(d2_all, jj, axis=0)[0]
+            vj = np.take_along_axis(var, jj, axis=0)[0]
+            rho = a * np.exp(-0.5 * d2j / vj) / (2.0 * np.pi * vj) ** (C / 2.0)
+        else:
+            raise ValueError(p.rho)
+        mu_upd = (1.0 - rho) * mu + rho * x[None, :, :]
         resid2 = ((x[None, :, :] - mu_upd) ** 2).sum(axis=1)
-        var_upd = np.maximum(p.var_min, (1.0 - a) * var + a * resid2)
+        var_upd = np.maximum(p.var_min, (1.0 - rho) * var + rho * resid2)
         mu_new = np.where(onehot[:, None, :], mu_upd, mu)
         var_new = np.where(onehot, var_upd, var)
         #    no match: the last rank is replaced by a new component centred on x

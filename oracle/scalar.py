@@ -24,11 +24,13 @@ class ScalarMixture:
     def state(self) -> Tuple[list, list, list]:
         return ([list(c[0]) for c in self.comps], [c[1] for c in self.comps], [c[2] for c in self.comps])
 
-    def step(self, x: Sequence[float]) -> bool:
+    def step(self, x: Sequence[float], hole=None) -> bool:
         p = self.p
         a = float(p.alpha)
         xs = [float(v) for v in x]
-        if p.hole_skip and self.C == 1 and xs[0] == 0.0:
+        if hole is None:
+            hole = p.hole_skip and self.C == 1 and xs[0] == 0.0
+        if hole:
             return False
 
         # which component explains x: the first live one, in rank order, inside k sigma
@@ -43,15 +45,22 @@ class ScalarMixture:
                 match = r
                 break
 
+        # rate of the mean and variance update
+        rate = a
+        if match is not None and p.rho == "density":
+            var_j = self.comps[match][1]
+            density = math.exp(-dist2 / (2.0 * var_j)) / math.pow(2.0 * math.pi * var_j, self.C / 2.0)
+            rate = a * density
+
         updated = []
         for r, (mean, var, weight) in enumerate(self.comps):
             weight = (1.0 - a) * weight + (a if r == match else 0.0)
             if r == match:
-                mean = [(1.0 - a) * mc + a * xc for mc, xc in zip(mean, xs)]
+                mean = [(1.0 - rate) * mc + rate * xc for mc, xc in zip(mean, xs)]
                 res = 0.0
                 for xc, mc in zip(xs, mean):
                     res += (xc - mc) * (xc - mc)
-                var = max(p.var_min, (1.0 - a) * var + a * res)
+                var = max(p.var_min, (1.0 - rate) * var + rate * res)
             updated.append([list(mean), var, weight])
         if match is None:
             updated[-1] = [list(xs), float(p.sigma0) ** 2, p.w_init]

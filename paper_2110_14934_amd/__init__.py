@@ -10,6 +10,7 @@ from __future__ import annotations
 
 from . import _abi
 from ._abi import (GMM_RGB, GMM_DEPTH, GMM_F32, GMM_F16, GMM_BF16, GMM_HOLE_SKIP, GMM_HOLE_AS_VALUE,
+                   GMM_SEPARATE, GMM_AUGMENTED, GMM_RHO_ALPHA, GMM_RHO_DENSITY, gmm_apply_frame_augmented,
                    GmmError, gmm_config, gmm_config_default, gmm_create, gmm_destroy, gmm_apply_frame,
                    gmm_fuse, gmm_apply_frame_fused, gmm_last_error, gmm_state_bytes, gmm_state_size,
                    gmm_read_state, gmm_write_state, gmm_version, stream_io, gmm_batch_create,
@@ -22,20 +23,34 @@ def mask_words(npix: int) -> int:
     return (npix + 63) // 64
 
 
+RHO_MODES = {"alpha": GMM_RHO_ALPHA, "density": GMM_RHO_DENSITY}
+
+
 class Segmenter:
-    """One stream's handle plus its output masks (torch tensors on the handle's device)."""
+    """One stream's handle plus its output masks (torch tensors on the handle's device).
+
+    ``rho`` = "alpha" | "density" picks the rate of the mean and variance updates. ``augmented``
+    builds the four-channel variant (both modalities, one mixture, mask in ``fg``) used by
+    ``apply_augmented``."""
 
     def __init__(self, width: int, height: int, modalities: int = GMM_RGB | GMM_DEPTH, M: int = 5,
-                 state_dtype: str = "f32", device: int = 0, **params):
+                 state_dtype: str = "f32", device: int = 0, rho: str = "alpha", augmented: bool = False,
+                 **params):
         import torch
         self.width, self.height, self.M = width, height, M
         self.modalities = modalities
         self.npix = width * height
+        self.augmented = augmented
         self.cfg = gmm_config_default(width, height, modalities, M, state_dtype=_abi.DTYPES[state_dtype],
-                                      device=device, **params)
+                                      device=device, rho_mode=RHO_MODES[rho],
+                                      variant=GMM_AUGMENTED if augmented else GMM_SEPARATE, **params)
         self.handle = gmm_create(self.cfg)
         dev = torch.device("cuda", device)
         n = mask_words(self.npix)
+        if augmented:
+            self.fg = torch.zeros(n, dtype=torch.int64, device=dev)
+            self.fg_rgb = self.fg_depth = self.fused = None
+            return
         self.fg_rgb = torch.zeros(n, dtype=torch.int64, device=dev) if modalities & GMM_RGB else None
         self.fg_depth = torch.zeros(n, dtype=torch.int64, device=dev) if modalities & GMM_DEPTH else None
         both = (modalities & GMM_RGB) and (modalities & GMM_DEPTH)
@@ -55,6 +70,11 @@ class Segmenter:
         rp, dp = self._pitches(rgb, depth)
         gmm_apply_frame_fused(self.handle, rgb, rp, depth, dp, self.fg_rgb, self.fg_depth, self.fused, stream)
         return self.fg_rgb, self.fg_depth, self.fused
+
+    def apply_augmented(self, rgb, depth, stream=None):
+        rp, dp = self._pitches(rgb, depth)
+        gmm_apply_frame_augmented(self.handle, rgb, rp, depth, dp, self.fg, stream)
+        return self.fg
 
     def fuse(self, fg_rgb, fg_depth, stream=None):
         gmm_fuse(self.handle, fg_rgb, fg_depth, self.fused, stream)

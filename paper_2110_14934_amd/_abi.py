@@ -25,6 +25,8 @@ GMM_RGB = 1
 GMM_DEPTH = 2
 GMM_F32, GMM_F16, GMM_BF16 = 0, 1, 2
 GMM_HOLE_SKIP, GMM_HOLE_AS_VALUE = 0, 1
+GMM_SEPARATE, GMM_AUGMENTED = 0, 1
+GMM_RHO_ALPHA, GMM_RHO_DENSITY = 0, 1
 
 DTYPES = {"f32": GMM_F32, "f16": GMM_F16, "bf16": GMM_BF16}
 
@@ -39,7 +41,7 @@ EXPORTS = (
     "gmm_exec_create", "gmm_exec_destroy", "gmm_exec_set_tuning", "gmm_exec_attach", "gmm_exec_detach",
     "gmm_exec_launch", "gmm_exec_poll", "gmm_exec_drain", "gmm_exec_now",
     "gmm_exec_stream_bytes", "gmm_exec_create_stream", "gmm_exec_destroy_stream",
-    "gmm_set_traffic_record",
+    "gmm_set_traffic_record", "gmm_apply_frame_augmented",
 )
 
 
@@ -57,6 +59,7 @@ class gmm_config(ctypes.Structure):
         ("sigma0", ctypes.c_float * 2), ("var_min", ctypes.c_float * 2),
         ("w_init", ctypes.c_float),
         ("hole_policy", ctypes.c_int32), ("state_dtype", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("variant", ctypes.c_int32), ("rho_mode", ctypes.c_int32),
     ]
 
 
@@ -136,6 +139,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "gmm_exec_create_stream": (st, [H, ctypes.POINTER(gmm_config), vp, ctypes.c_size_t, ctypes.POINTER(H)]),
         "gmm_exec_destroy_stream": (st, [H, H]),
         "gmm_set_traffic_record": (st, [H, vp]),
+        "gmm_apply_frame_augmented": (st, [H, vp, i64, vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -199,6 +203,11 @@ def gmm_fuse(h, fg_rgb, fg_depth, fused, stream=None):
 def gmm_apply_frame_fused(h, rgb, rgb_pitch, depth, depth_pitch, fg_rgb, fg_depth, fused, stream=None):
     _check(load().gmm_apply_frame_fused(h, _ptr(rgb), rgb_pitch, _ptr(depth), depth_pitch, _ptr(fg_rgb),
                                         _ptr(fg_depth), _ptr(fused), _stream(stream)))
+
+
+def gmm_apply_frame_augmented(h, rgb, rgb_pitch, depth, depth_pitch, fg, stream=None):
+    _check(load().gmm_apply_frame_augmented(h, _ptr(rgb), rgb_pitch, _ptr(depth), depth_pitch, _ptr(fg),
+                                            _stream(stream)))
 
 
 def gmm_last_error() -> str:

@@ -126,12 +126,19 @@ static gmm_status validate_config(const gmm_config* c) {
   if (c->state_dtype != GMM_F32 && c->state_dtype != GMM_F16 && c->state_dtype != GMM_BF16)
     return fail(GMM_ERR_INVALID_ARG, "state_dtype must be GMM_F32, GMM_F16 or GMM_BF16");
   if (c->device < 0) return fail(GMM_ERR_INVALID_ARG, "device must be >= 0");
+  if (c->variant != GMM_SEPARATE && c->variant != GMM_AUGMENTED)
+    return fail(GMM_ERR_INVALID_ARG, "variant must be GMM_SEPARATE or GMM_AUGMENTED");
+  if (c->variant == GMM_AUGMENTED && c->modalities != (GMM_RGB | GMM_DEPTH))
+    return fail(GMM_ERR_INVALID_ARG, "the augmented variant needs both modalities");
+  if (c->rho_mode != GMM_RHO_ALPHA && c->rho_mode != GMM_RHO_DENSITY)
+    return fail(GMM_ERR_INVALID_ARG, "rho_mode must be GMM_RHO_ALPHA or GMM_RHO_DENSITY");
   if (!frame_variant_compiled(c->M, c->state_dtype))
     return fail(GMM_ERR_UNSUPPORTED, "this (M, state dtype) is not compiled");
   return GMM_OK;
 }
 
-static ModelConsts make_consts(const gmm_config& c, int mod, bool hole_skip) {
+// Constants of one mixture over C channels; `mod` picks sigma0 / var_min (0 colour, 1 depth).
+static ModelConsts make_consts(const gmm_config& c, int mod, int C, bool hole_skip) {
   ModelConsts k{};
   k.alpha = c.alpha;
   k.oma = 1.0f - c.alpha;
@@ -141,6 +148,8 @@ static ModelConsts make_consts(const gmm_config& c, int mod, bool hole_skip) {
   k.var_min = c.var_min[mod];
   k.w_init = c.w_init;
   k.hole_skip = hole_skip ? 1 : 0;
+  k.rho_density = c.rho_mode == GMM_RHO_DENSITY ? 1 : 0;
+  k.rho_scale = static_cast<float>(static_cast<double>(c.alpha) * std::pow(2.0 * M_PI, -0.5 * C));
   return k;
 }
 
@@ -169,6 +178,8 @@ gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, in
   cfg->hole_policy = GMM_HOLE_SKIP;
   cfg->state_dtype = GMM_F32;
   cfg->device = 0;
+  cfg->variant = GMM_SEPARATE;
+  cfg->rho_mode = GMM_RHO_ALPHA;
   return GMM_OK;
 }
 
@@ -185,15 +196,20 @@ gmm_status rgbd::new_handle(const gmm_config* cfg, gmm_handle** out) {
   h->tiles64 = static_cast<uint32_t>((h->npix + kWave - 1) / kWave);
   h->esize = dtype_size(cfg->state_dtype);
   const size_t plane = static_cast<size_t>(h->tiles64) * kWave * h->esize;  // one plane, all tiles
-  h->rgb_bytes = has_rgb(h) ? plane * 5 * cfg->M : 0;
-  h->depth_bytes = has_depth(h) ? plane * 3 * cfg->M : 0;
-  h->fuse_bytes = has_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
+  h->rgb_bytes = is_augmented(h) ? plane * 6 * cfg->M : (has_rgb(h) ? plane * 5 * cfg->M : 0);
+  h->depth_bytes = sep_depth(h) ? plane * 3 * cfg->M : 0;
+  h->fuse_bytes = sep_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
   if (std::max(h->rgb_bytes, h->depth_bytes) > 0xFFFFFFFFull) {
     delete h;
     return fail(GMM_ERR_INVALID_ARG, "one modality's state must stay below 4 GiB (too many pixels for this M)");
   }
-  h->kc = make_consts(*cfg, 0, false);
-  h->kd = make_consts(*cfg, 1, cfg->hole_policy == GMM_HOLE_SKIP);
+  if (is_augmented(h)) {
+    h->kc = make_consts(*cfg, 0, 4, cfg->hole_policy == GMM_HOLE_SKIP);
+    h->kd = h->kc;
+  } else {
+    h->kc = make_consts(*cfg, 0, 3, false);
+    h->kd = make_consts(*cfg, 1, 1, cfg->hole_policy == GMM_HOLE_SKIP);
+  }
   *out = h;
   return GMM_OK;
 }
@@ -202,16 +218,17 @@ void rgbd::place_state(gmm_handle* h, void* mem) {
   h->mem = mem;
   uint8_t* base = static_cast<uint8_t*>(mem);
   h->st_rgb = has_rgb(h) ? base : nullptr;
-  h->st_depth = has_depth(h) ? base + h->rgb_bytes : nullptr;
-  h->fstate = has_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
+  h->st_depth = sep_depth(h) ? base + h->rgb_bytes : nullptr;
+  h->fstate = sep_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
 }
 
 hipError_t rgbd::init_state(gmm_handle* h, hipStream_t s) {
   hipError_t e = hipSuccess;
-  if (has_rgb(h)) e = launch_init(h->st_rgb, h->cfg.state_dtype, h->tiles64, h->cfg.M, 3, h->kc.var0, s);
-  if (e == hipSuccess && has_depth(h))
+  if (has_rgb(h))
+    e = launch_init(h->st_rgb, h->cfg.state_dtype, h->tiles64, h->cfg.M, is_augmented(h) ? 4 : 3, h->kc.var0, s);
+  if (e == hipSuccess && sep_depth(h))
     e = launch_init(h->st_depth, h->cfg.state_dtype, h->tiles64, h->cfg.M, 1, h->kd.var0, s);
-  if (e == hipSuccess && has_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, s);
+  if (e == hipSuccess && sep_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, s);
   return e;
 }
 
@@ -284,7 +301,8 @@ gmm_status gmm_state_bytes(const gmm_handle* h, size_t* device_bytes) {
 gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles) {
   if (!h || !n_doubles) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
   const size_t n = static_cast<size_t>(h->npix), M = static_cast<size_t>(h->cfg.M);
-  *n_doubles = (has_rgb(h) ? 5 * M * n : 0) + (has_depth(h) ? 3 * M * n : 0) + (has_both(h) ? 2 * n : 0);
+  *n_doubles = is_augmented(h) ? 6 * M * n
+                               : (has_rgb(h) ? 5 * M * n : 0) + (has_depth(h) ? 3 * M * n : 0) + (has_both(h) ? 2 * n : 0);
   return GMM_OK;
 }
 
@@ -294,6 +312,7 @@ gmm_status rgbd::check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb
                                    const uint16_t* depth, int64_t depth_pitch, uint64_t* fg_rgb,
                                    uint64_t* fg_depth) {
   if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
+  if (is_augmented(h)) return fail(GMM_ERR_STATE, "an augmented handle runs through gmm_apply_frame_augmented");
   const gmm_config& c = h->cfg;
   if (has_rgb(h)) {
     if (!rgb || !fg_rgb) return fail(GMM_ERR_INVALID_ARG, "colour handle needs rgb and fg_rgb");
@@ -337,7 +356,8 @@ FrameArgs rgbd::frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,
   a.fused = fused;
   a.kc = h->kc;
   a.kd = h->kd;
-  a.mode = (has_rgb(h) ? kModeRGB : 0) | (has_depth(h) ? kModeDepth : 0) | (fused ? kModeFuse : 0);
+  a.mode = is_augmented(h) ? kModeAug
+                           : (has_rgb(h) ? kModeRGB : 0) | (has_depth(h) ? kModeDepth : 0) | (fused ? kModeFuse : 0);
   a.wave_bytes = h->wave_bytes;
   return a;
 }
@@ -363,7 +383,7 @@ gmm_status gmm_apply_frame(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_
 gmm_status gmm_fuse(gmm_handle* h, const uint64_t* fg_rgb, const uint64_t* fg_depth, uint64_t* fused,
                     void* stream) {
   if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
-  if (!has_both(h)) return fail(GMM_ERR_STATE, "fusion needs a handle with both modalities");
+  if (!sep_both(h)) return fail(GMM_ERR_STATE, "fusion needs a handle with both separate modalities");
   if (!fg_rgb || !fg_depth || !fused) return fail(GMM_ERR_INVALID_ARG, "NULL mask");
   if ((reinterpret_cast<uintptr_t>(fg_rgb) | reinterpret_cast<uintptr_t>(fg_depth) |
        reinterpret_cast<uintptr_t>(fused)) % 8)
@@ -382,7 +402,7 @@ gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_
                                  uint64_t* fg_rgb, uint64_t* fg_depth, uint64_t* fused,
                                  void* stream) {
   if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
-  if (!has_both(h)) return fail(GMM_ERR_STATE, "fusion needs a handle with both modalities");
+  if (!sep_both(h)) return fail(GMM_ERR_STATE, "fusion needs a handle with both separate modalities");
   gmm_status st = check_frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth);
   if (st != GMM_OK) return st;
   if (!fused || reinterpret_cast<uintptr_t>(fused) % 8)
@@ -393,6 +413,28 @@ gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeRGB | kModeDepth | kModeFuse, s);
   if (e != hipSuccess) return hip_fail(e, "fused frame kernel launch");
+  h->last_stream = s;
+  return GMM_OK;
+}
+
+gmm_status gmm_apply_frame_augmented(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_bytes,
+                                     const uint16_t* depth, int64_t depth_pitch_bytes, uint64_t* fg,
+                                     void* stream) {
+  if (!h) return fail(GMM_ERR_INVALID_ARG, "handle is NULL");
+  if (!is_augmented(h)) return fail(GMM_ERR_STATE, "not a GMM_AUGMENTED handle");
+  if (!rgb || !depth || !fg) return fail(GMM_ERR_INVALID_ARG, "rgb, depth and fg are required");
+  const int64_t w = h->cfg.width;
+  if (rgb_pitch_bytes < 3 * w) return fail(GMM_ERR_INVALID_ARG, "rgb pitch < 3*width");
+  if (depth_pitch_bytes < 2 * w || depth_pitch_bytes % 2)
+    return fail(GMM_ERR_INVALID_ARG, "depth pitch must be even and >= 2*width");
+  if (reinterpret_cast<uintptr_t>(depth) % 2) return fail(GMM_ERR_INVALID_ARG, "depth not 2-byte aligned");
+  if (reinterpret_cast<uintptr_t>(fg) % 8) return fail(GMM_ERR_INVALID_ARG, "fg not 8-byte aligned");
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  const FrameArgs a = frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg, nullptr, nullptr);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeAug, s);
+  if (e != hipSuccess) return hip_fail(e, "augmented frame kernel launch");
   h->last_stream = s;
   return GMM_OK;
 }
@@ -416,9 +458,9 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
   double* o = host_out;
   size_t off = 0;
   for (int blk = 0; blk < 2; ++blk) {
-    const bool present = blk == 0 ? has_rgb(h) : has_depth(h);
+    const bool present = blk == 0 ? has_rgb(h) : sep_depth(h);
     if (!present) continue;
-    const size_t P = blk == 0 ? 5 : 3;
+    const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const size_t tile_bytes = P * M * kWave * h->esize;
     // tiled device layout -> canonical [param][rank][pixel]
     const uint32_t nv = static_cast<uint32_t>(P * M);
@@ -434,7 +476,7 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     }
     off += tile_bytes * h->tiles64;
   }
-  if (has_both(h)) {
+  if (sep_both(h)) {
     const uint8_t* f = raw.data() + off;
     for (size_t i = 0; i < n; ++i) o[i] = static_cast<double>((f[i] >> 3) & 1u);
     o += n;
@@ -456,9 +498,9 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
   const double* in = host_in;
   size_t off = 0;
   for (int blk = 0; blk < 2; ++blk) {
-    const bool present = blk == 0 ? has_rgb(h) : has_depth(h);
+    const bool present = blk == 0 ? has_rgb(h) : sep_depth(h);
     if (!present) continue;
-    const size_t P = blk == 0 ? 5 : 3;
+    const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const size_t tile_bytes = P * M * kWave * h->esize;
     // canonical [param][rank][pixel] -> tiled device layout
     const uint32_t nv = static_cast<uint32_t>(P * M);
@@ -474,7 +516,7 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     }
     off += tile_bytes * h->tiles64;
   }
-  if (has_both(h)) {
+  if (sep_both(h)) {
     uint8_t* f = raw.data() + off;
     for (size_t i = 0; i < n; ++i) {
       const double I = in[i], c = in[n + i];

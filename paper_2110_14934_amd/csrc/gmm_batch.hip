@@ -210,6 +210,7 @@ gmm_status gmm_batch_create(gmm_handle* const* handles, int32_t n, int32_t n_slo
     const gmm_handle* h = handles[i];
     if (!h) return fail(GMM_ERR_INVALID_ARG, "NULL handle in batch");
     if (!seen.insert(h).second) return fail(GMM_ERR_INVALID_ARG, "a handle appears twice in the batch");
+    if (is_augmented(h)) return fail(GMM_ERR_UNSUPPORTED, "augmented handles run one at a time");
     if (h->cfg.device != handles[0]->cfg.device || h->cfg.M != handles[0]->cfg.M ||
         h->cfg.state_dtype != handles[0]->cfg.state_dtype)
       return fail(GMM_ERR_INVALID_ARG, "all handles of a batch need the same device, M and state dtype");

@@ -26,6 +26,8 @@ struct ModelConsts {
   float var_min;   // variance floor
   float w_init;    // weight of a new component before renormalisation
   int32_t hole_skip;  // depth: value 0 leaves the state untouched, pixel background
+  int32_t rho_density;  // 0: mean/variance rate alpha; 1: alpha times the matched density
+  float rho_scale;      // alpha (2 pi)^(-C/2), the constant factor of that density rate
 };
 
 // ---- storage types of the mixture state --------------------------------------------------
@@ -242,7 +244,9 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
 // and `q_out` the rank the updated (or new) component ends up at.
 //   match    : first live rank, in stored (w/sigma descending) order, with |x-mu|^2 < k^2 var
 //   weights  : w <- (1-alpha) w + alpha [matched]
-//   matched  : mu <- (1-alpha) mu + alpha x ; var <- max(var_min, (1-alpha) var + alpha |x-mu_new|^2)
+//   matched  : mu <- (1-rho) mu + rho x ; var <- max(var_min, (1-rho) var + rho |x-mu_new|^2), with
+//              rho = alpha, or (variant) rho = alpha * N(x | mu, var I), the isotropic Gaussian
+//              density of x under the matched component before its update
 //   no match : the last rank becomes (x, sigma0^2, w_init)
 //   then     : w <- w / sum(w); re-sort by w/sigma descending; B = min{b : w_0+...+w_{b-1} > T};
 //              foreground = no match or new rank >= B
@@ -256,6 +260,7 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
                                          int& q_out) {
   // match, in rank order
   int j = M;
+  float d2j = 0.f;  // squared distance to the matched component
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     float d2 = 0.f;
@@ -265,7 +270,9 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       d2 = fmaf(t, t, d2);
     }
     const bool hit = (s.w[r] > 0.f) & (d2 < k.k2 * s.var[r]);  // no short-circuit: no branch
-    j = ((j == M) & hit) ? r : j;
+    const bool take = (j == M) & hit;
+    d2j = take ? d2 : d2j;
+    j = take ? r : j;
   }
   const bool matched = j < M;
   const int t = matched ? j : M - 1;
@@ -283,13 +290,30 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
     for (int c = 0; c < C; ++c) mj[c] = isj ? s.mu[c][r] : mj[c];
   }
   float d2n = 0.f;
+  if (k.rho_density) {  // uniform over the wave
+    // rho = alpha (2 pi var)^(-C/2) exp(-d2 / (2 var)), with exp(y) = 2^(y log2 e); the
+    // update is written as an increment, which keeps a rate of 1e-5 from drowning in rounding
+    const float rv = __builtin_amdgcn_rcpf(vj);
+    float dens = (C & 1) ? __builtin_amdgcn_rsqf(vj) : 1.f;
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
-    const float tt = x[c] - mj[c];
-    d2n = fmaf(tt, tt, d2n);
+    for (int c = 0; c < C / 2; ++c) dens *= rv;
+    const float rho = k.rho_scale * dens * __builtin_amdgcn_exp2f(-0.72134752f * d2j * rv);  // -log2(e)/2
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      mj[c] = fmaf(rho, x[c] - mj[c], mj[c]);
+      const float tt = x[c] - mj[c];
+      d2n = fmaf(tt, tt, d2n);
+    }
+    vj = fmaxf(k.var_min, fmaf(rho, d2n - vj, vj));
+  } else {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
+      const float tt = x[c] - mj[c];
+      d2n = fmaf(tt, tt, d2n);
+    }
+    vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
   }
-  vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
   wj = fmaf(k.oma, wj, k.alpha);
   // no match: the least probable (last-ranked) component is replaced
   float tmu[C], tvar, tw;

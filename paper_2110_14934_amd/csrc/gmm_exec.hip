@@ -232,6 +232,7 @@ gmm_status gmm_exec_set_tuning(gmm_exec* x, const gmm_batch_tuning* t) {
 gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes) {
   if (!x || !h) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
   if (h->cfg.device != x->device) return fail(GMM_ERR_INVALID_ARG, "handle lives on another device");
+  if (is_augmented(h)) return fail(GMM_ERR_UNSUPPORTED, "augmented handles run one at a time");
   std::lock_guard<std::mutex> lk(x->mu);
   if (x->attached.count(h)) return fail(GMM_ERR_INVALID_ARG, "handle already attached");
   if (x->M >= 0 && (h->cfg.M != x->M || h->cfg.state_dtype != x->dtype))
@@ -442,6 +443,10 @@ gmm_status gmm_exec_stream_bytes(const gmm_config* cfg, size_t* bytes) {
   gmm_handle* h = nullptr;
   gmm_status st = new_handle(cfg, &h);
   if (st != GMM_OK) return st;
+  if (is_augmented(h)) {
+    delete h;
+    return fail(GMM_ERR_UNSUPPORTED, "augmented handles run one at a time");
+  }
   const size_t n = static_cast<size_t>(h->npix);
   const size_t slot = (has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0) + (has_depth(h) ? (n * 2 + 255) / 256 * 256 : 0);
   *bytes = (state_bytes(h) + 255) / 256 * 256 + slot;

@@ -82,14 +82,27 @@ __device__ __forceinline__ bool step_modality(const StateBlock& blk, uint32_t p,
 }
 
 // Pixel p of stream `a` (p may lie past the end: such lanes only take part in the ballots).
-// `mode` must be uniform over the wave.
-template <int M, typename S>
+// `mode` must be uniform over the wave. AUG compiles the four-channel variant in (kModeAug):
+// one mixture over (R, G, B, D8) with D8 = min(255, depth >> 4), the augmentation the paper
+// describes and rejects in Sec. III.B; its mask goes to fg_rgb.
+template <int M, typename S, bool AUG = false>
 __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint32_t p, int lane,
                                               uint32_t* lds_wave) {
   const uint32_t wave_base = p - lane;
   const bool valid = p < a.npix;
   bool fgc = false, fgd = false;
   uint32_t wave_bytes = 0;
+  if (AUG && (mode & kModeAug) != 0) {
+    float x3[3];
+    load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x3);
+    const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
+    const bool active = valid && !(a.kc.hole_skip && d == 0u);
+    const float x[4] = {x3[0], x3[1], x3[2], static_cast<float>(min(d >> 4, 255u))};
+    const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 6 * M);
+    const bool fg = step_modality<M, 4, S>(blk, p, valid, active, x, a.kc, wave_bytes);
+    const uint64_t bits = __ballot(fg);
+    if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
+  }
   if ((mode & kModeRGB) != 0) {
     float x[3];
     load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);

@@ -23,7 +23,7 @@ struct FrameArgs {
   int64_t rgb_pitch;
   const uint16_t* depth;
   int64_t depth_pitch;
-  void* st_rgb;            // colour state block: 5*M planes
+  void* st_rgb;            // colour state block: 5*M planes (four-channel variant: 6*M)
   void* st_depth;          // depth state block: 3*M planes
   uint8_t* fstate;         // List 1 state bytes
   uint64_t* fg_rgb;
@@ -36,7 +36,7 @@ struct FrameArgs {
   uint64_t* wave_bytes;    // optional: per-wave running total of state bytes moved (measurement)
 };
 
-enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4 };
+enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4, kModeAug = 8 };
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStream_t s);
@@ -97,6 +97,12 @@ struct gmm_handle {  // the library's per-stream object (opaque in gmm.h)
 inline bool has_rgb(const gmm_handle* h) { return (h->cfg.modalities & GMM_RGB) != 0; }
 inline bool has_depth(const gmm_handle* h) { return (h->cfg.modalities & GMM_DEPTH) != 0; }
 inline bool has_both(const gmm_handle* h) { return has_rgb(h) && has_depth(h); }
+// the four-channel (R, G, B, depth byte) variant: one mixture, no separate models, no fusion
+inline bool is_augmented(const gmm_handle* h) { return h->cfg.variant == GMM_AUGMENTED; }
+// the per-modality separate models of the method (colour block, depth block, List 1 state)
+inline bool sep_rgb(const gmm_handle* h) { return has_rgb(h) && !is_augmented(h); }
+inline bool sep_depth(const gmm_handle* h) { return has_depth(h) && !is_augmented(h); }
+inline bool sep_both(const gmm_handle* h) { return has_both(h) && !is_augmented(h); }
 
 namespace rgbd {
 // Validation and kernel arguments of one stream's frame (shared by the plain and batched paths).

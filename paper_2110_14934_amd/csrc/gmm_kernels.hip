@@ -14,13 +14,14 @@
 
 namespace rgbd {
 
-// One stream, one frame. MODE is a combination of kModeRGB, kModeDepth, kModeFuse.
+// One stream, one frame. MODE is a combination of kModeRGB, kModeDepth, kModeFuse, or kModeAug
+// alone (the four-channel variant).
 template <int M, typename S, int MODE>
 __global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
   __shared__ uint32_t lds[kWavesPerBlock][48];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  process_pixel<M, S>(a, MODE, blockIdx.x * kBlock + threadIdx.x, lane, lds[wv]);
+  process_pixel<M, S, (MODE & kModeAug) != 0>(a, MODE, blockIdx.x * kBlock + threadIdx.x, lane, lds[wv]);
 }
 
 // Standalone List 1 over two given masks.
@@ -81,6 +82,7 @@ static hipError_t launch_frame_ms(const FrameArgs& a, int mode, hipStream_t s) {
     case kModeRGB | kModeDepth | kModeFuse:
       frame_kernel<M, S, kModeRGB | kModeDepth | kModeFuse><<<g, b, 0, s>>>(a);
       break;
+    case kModeAug: frame_kernel<M, S, kModeAug><<<g, b, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

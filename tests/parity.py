@@ -92,3 +92,14 @@ def param_mismatch(gpu, ora) -> np.ndarray:
 
 def oracle_state(o):
     return (o.mu, o.var, o.w)
+
+
+def aug_to_canonical(o) -> np.ndarray:
+    """Four-channel oracle state -> canonical layout (muR, muG, muB, muD8, var, w; rank-major)."""
+    mu, var, w = o.get_state()
+    return np.concatenate([mu[:, c, :].ravel() for c in range(4)] + [var.ravel(), w.ravel()])
+
+
+def aug_from_canonical(flat: np.ndarray, M: int, n: int):
+    blk = flat.reshape(6, M, n)
+    return (np.stack([blk[0], blk[1], blk[2], blk[3]], axis=1), blk[4], blk[5])

@@ -46,6 +46,7 @@ def test_version_and_defaults(lib):
     assert list(cfg.sigma0) == [30.0, 50.0] and list(cfg.var_min) == [9.0, 25.0]
     assert cfg.w_init == pytest.approx(0.01)
     assert cfg.hole_policy == _abi.GMM_HOLE_SKIP and cfg.state_dtype == _abi.GMM_F32
+    assert cfg.variant == _abi.GMM_SEPARATE and cfg.rho_mode == _abi.GMM_RHO_ALPHA
 
 
 @pytest.mark.parametrize("field,value,needle", [
@@ -53,7 +54,8 @@ def test_version_and_defaults(lib):
     ("modalities", 4, "modalities"), ("M", 0, "M must"), ("M", 6, "M must"),
     ("alpha", 0.0, "alpha"), ("alpha", 1.5, "alpha"), ("k", 0.0, "k must"), ("T", 1.0, "T must"),
     ("T", 0.0, "T must"), ("w_init", 0.0, "w_init"), ("hole_policy", 7, "hole_policy"),
-    ("state_dtype", 9, "state_dtype"), ("device", -1, "device"),
+    ("state_dtype", 9, "state_dtype"), ("device", -1, "device"), ("variant", 2, "variant"),
+    ("rho_mode", 5, "rho_mode"),
 ])
 def test_create_rejects_bad_config_without_device(lib, field, value, needle):
     cfg = _abi.gmm_config_default(64, 48, 3, 3)
@@ -120,5 +122,18 @@ def test_batch_struct_layouts(lib):
 
 
 def test_config_struct_layout_matches_header(lib):
-    # 4 ints, 3 floats, 2x2 floats, 1 float, 3 ints = 15 four-byte fields
-    assert ctypes.sizeof(_abi.gmm_config) == 15 * 4
+    # 4 ints, 3 floats, 2x2 floats, 1 float, 5 ints = 17 four-byte fields
+    assert ctypes.sizeof(_abi.gmm_config) == 17 * 4
+
+
+def test_augmented_variant_needs_both_modalities_and_runs_alone(lib):
+    for mods in (_abi.GMM_RGB, _abi.GMM_DEPTH):
+        cfg = _abi.gmm_config_default(64, 48, mods, 3, variant=_abi.GMM_AUGMENTED)
+        with pytest.raises(_abi.GmmError) as e:
+            _abi.gmm_create(cfg)
+        assert e.value.status == _abi.GMM_ERR_INVALID_ARG and "both modalities" in str(e.value)
+    # the serving executor sizes a stream before it allocates: an augmented one is refused there
+    cfg = _abi.gmm_config_default(64, 48, 3, 3, variant=_abi.GMM_AUGMENTED)
+    n = ctypes.c_size_t()
+    assert lib.gmm_exec_stream_bytes(ctypes.byref(cfg), ctypes.byref(n)) == _abi.GMM_ERR_UNSUPPORTED
+    assert lib.gmm_apply_frame_augmented(None, None, 0, None, 0, None, None) == _abi.GMM_ERR_INVALID_ARG

@@ -29,12 +29,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def mix_params(mix: MixtureSettings, modality: str) -> MixParams:
+def mix_params(mix: MixtureSettings, modality: str, rho: str = "alpha") -> MixParams:
     if modality == "rgb":
         return MixParams(M=mix.M, alpha=mix.alpha, k=mix.k, T=mix.T, sigma0=mix.sigma0_rgb,
-                         var_min=mix.var_min_rgb, w_init=mix.w_init)
+                         var_min=mix.var_min_rgb, w_init=mix.w_init, rho=rho)
     return MixParams(M=mix.M, alpha=mix.alpha, k=mix.k, T=mix.T, sigma0=mix.sigma0_depth,
-                     var_min=mix.var_min_depth, w_init=mix.w_init, hole_skip=mix.hole_skip)
+                     var_min=mix.var_min_depth, w_init=mix.w_init, hole_skip=mix.hole_skip, rho=rho)
 
 
 def seg_kwargs(mix: MixtureSettings):
@@ -48,14 +48,14 @@ def _frames(st: Stream, t: int):
 
 
 def _lockstep(spec: StreamSpec, mix: MixtureSettings, frames: int, dtype: str = "f32", fused=True,
-              pitch_pad=0, misalign=False):
+              pitch_pad=0, misalign=False, rho="alpha"):
     """Run lockstep parity; returns (mask disagreements, pixel-frames)."""
     st = Stream(spec)
     n, M = spec.npix, mix.M
     mods = (GMM_RGB if spec.rgb else 0) | (GMM_DEPTH if spec.depth else 0)
-    seg = Segmenter(spec.width, spec.height, mods, M, state_dtype=dtype, **seg_kwargs(mix))
-    col = MixtureOracle(mix_params(mix, "rgb"), 3, n) if spec.rgb else None
-    dep = MixtureOracle(mix_params(mix, "depth"), 1, n) if spec.depth else None
+    seg = Segmenter(spec.width, spec.height, mods, M, state_dtype=dtype, rho=rho, **seg_kwargs(mix))
+    col = MixtureOracle(mix_params(mix, "rgb", rho), 3, n) if spec.rgb else None
+    dep = MixtureOracle(mix_params(mix, "depth", rho), 1, n) if spec.depth else None
     both = spec.rgb and spec.depth
     fus = FusionOracle(n) if both else None
     storage = dtype

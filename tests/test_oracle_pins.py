@@ -363,3 +363,140 @@ def test_storage_rounding_matches_torch_conversions():
     np.testing.assert_array_equal(round_to_storage(small, "f16"), f16_t)
     assert round_to_storage(np.array([1 + 2 ** -8]), "bf16")[0] == 1.0          # tie -> even
     assert round_to_storage(np.array([1 + 3 * 2 ** -8]), "bf16")[0] == 1 + 2 ** -6
+
+
+# ---- the ablation variants: density rate, four-channel augmentation ----------------------
+
+@pytest.mark.parametrize("C", [1, 3, 4])
+def test_density_rate_matches_scipy_gaussian_pdf(C):
+    # One live component, x inside k sigma: the mean moves towards x by the fraction rho, which
+    # must equal alpha times scipy's multivariate normal density N(x | mu, var I) (an independent
+    # evaluation of the density: normalisation, power of 2 pi, the 1/2 in the exponent).
+    from scipy.stats import multivariate_normal
+    rng = np.random.default_rng(40 + C)
+    n, a = 24, 0.3
+    p = MixParams(M=2, alpha=a, k=2.5, T=0.7, sigma0=30.0, var_min=1e-6, w_init=a, rho="density")
+    o = MixtureOracle(p, C, n)
+    mu = rng.uniform(50, 200, size=(n, C))
+    var = rng.uniform(0.5, 40.0, size=n)                        # small variances: rho up to ~0.1
+    o.set_state(np.stack([mu.T, np.zeros((C, n))]), np.stack([var, np.full(n, 900.0)]),
+                np.stack([np.ones(n), np.zeros(n)]))
+    x = mu + rng.normal(0, 1, size=(n, C)) * np.sqrt(var)[:, None] * 0.8
+    x[0] = mu[0]                                                # d = 0: rho = alpha (2 pi var)^(-C/2)
+    info = o.step(x)
+    for i in range(n):
+        d2 = float(((x[i] - mu[i]) ** 2).sum())
+        if d2 >= 6.25 * var[i]:
+            assert not info.matched[i]
+            continue
+        assert info.matched[i]
+        pdf = multivariate_normal.pdf(x[i], mean=mu[i], cov=var[i] * np.eye(C))
+        r = 0 if o.w[0, i] > o.w[1, i] and o.var[0, i] != 900.0 else 1
+        new_mu = o.mu[r, :, i]
+        if i == 0:
+            np.testing.assert_allclose(new_mu, mu[0], rtol=0, atol=1e-12)
+            continue
+        c = int(np.argmax(np.abs(x[i] - mu[i])))
+        rho = (new_mu[c] - mu[i, c]) / (x[i, c] - mu[i, c])
+        assert rho == pytest.approx(a * pdf, rel=1e-9), i
+        # every channel moves by the same fraction
+        np.testing.assert_allclose(new_mu - mu[i], rho * (x[i] - mu[i]), rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("C", [1, 3, 4])
+@pytest.mark.parametrize("M", [3, 5])
+def test_density_rate_vectorised_equals_scalar(M, C):
+    rng = np.random.default_rng(700 + 10 * M + C)
+    n, T = 16, 40
+    p = MixParams(M=M, alpha=0.3, k=2.5, T=0.6, sigma0=6.0, var_min=0.25, w_init=0.2, rho="density")
+    vec = MixtureOracle(p, C, n)
+    sca = [ScalarMixture(p, C) for _ in range(n)]
+    for x in _random_stream(rng, n, C, T, spread=1.5):
+        info = vec.step(x)
+        for i in range(n):
+            assert sca[i].step(x[i]) == bool(info.fg[i])
+            mu_s, var_s, w_s = sca[i].state()
+            np.testing.assert_allclose(w_s, vec.w[:, i], rtol=1e-12, atol=1e-15)
+            np.testing.assert_allclose(var_s, vec.var[:, i], rtol=1e-12)
+            np.testing.assert_allclose(np.array(mu_s), vec.mu[:, :, i], rtol=1e-12, atol=1e-12)
+
+
+def test_density_rate_differs_from_alpha_rate():
+    # the two readings of rho must give different means on the same input (a variant that
+    # silently fell back to alpha would pass every other density pin with rho = alpha ...
+    # except this one)
+    rng = np.random.default_rng(5)
+    n = 32
+    xs = _random_stream(rng, n, 3, 20, spread=3.0)
+    base = dict(M=3, alpha=0.1, k=2.5, T=0.7, sigma0=20.0, var_min=4.0, w_init=0.1)
+    oa = MixtureOracle(MixParams(**base), 3, n)
+    od = MixtureOracle(MixParams(**base, rho="density"), 3, n)
+    for x in xs:
+        oa.step(x)
+        od.step(x)
+    assert np.abs(oa.mu - od.mu).max() > 0.1
+
+
+def test_depth_byte_hand_values():
+    from oracle import depth_byte
+    d = np.array([0, 1, 15, 16, 17, 31, 32, 1200, 2000, 4079, 4080, 4095, 4096, 65535])
+    assert depth_byte(d).tolist() == [0, 0, 0, 1, 1, 1, 2, 75, 125, 254, 255, 255, 255, 255]
+
+
+def test_vectorised_equals_scalar_four_channels():
+    rng = np.random.default_rng(404)
+    n, T = 16, 30
+    p = MixParams(M=4, alpha=0.2, k=2.5, T=0.7, sigma0=15.0, var_min=4.0, w_init=0.1)
+    vec = MixtureOracle(p, 4, n)
+    sca = [ScalarMixture(p, 4) for _ in range(n)]
+    for x in _random_stream(rng, n, 4, T, spread=6.0):
+        info = vec.step(x)
+        for i in range(n):
+            assert sca[i].step(x[i]) == bool(info.fg[i])
+            mu_s, var_s, w_s = sca[i].state()
+            np.testing.assert_allclose(w_s, vec.w[:, i], rtol=1e-12, atol=1e-15)
+            np.testing.assert_allclose(var_s, vec.var[:, i], rtol=1e-12)
+            np.testing.assert_allclose(np.array(mu_s), vec.mu[:, :, i], rtol=1e-12, atol=1e-12)
+
+
+def test_augmented_with_constant_depth_is_the_colour_model():
+    # A depth byte that never changes adds nothing to any distance once a component holds it,
+    # so the four-channel model must reproduce the three-channel colour model: same masks,
+    # variances, weights and colour means; the depth mean stays at the byte.
+    from oracle import AugmentedOracle
+    rng = np.random.default_rng(8)
+    n, T = 48, 40
+    p = MixParams(M=4, alpha=0.05, k=2.5, T=0.7, sigma0=30.0, var_min=9.0, w_init=0.05, hole_skip=True)
+    aug = AugmentedOracle(p, n)
+    col = MixtureOracle(p, 3, n)
+    depth = np.full(n, 2000, dtype=np.uint16)              # byte 125
+    for rgb in _random_stream(rng, n, 3, T, spread=5.0):
+        ia = aug.step(rgb, depth)
+        ic = col.step(rgb)
+        np.testing.assert_array_equal(ia.fg, ic.fg)
+        mu, var, w = aug.get_state()
+        np.testing.assert_allclose(var, col.var, rtol=1e-12)
+        np.testing.assert_allclose(w, col.w, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(mu[:, :3], col.mu, rtol=1e-12, atol=1e-12)
+        live = w > 0
+        np.testing.assert_allclose(mu[:, 3][live], 125.0, rtol=1e-12)
+
+
+def test_augmented_depth_change_alone_is_foreground_and_holes_are_skipped():
+    # fixed colour; after the background settles, a depth jump of 400 mm (25 bytes) alone must
+    # make the pixel foreground (25^2 = 625 > k^2 var with var at its floor 9 is not needed:
+    # the settled variance is at the floor); a hole leaves the state untouched, background
+    from oracle import AugmentedOracle
+    p = MixParams(M=3, alpha=0.05, k=2.5, T=0.7, sigma0=30.0, var_min=9.0, w_init=0.05, hole_skip=True)
+    aug = AugmentedOracle(p, 1)
+    rgb = np.array([[100, 120, 140]])
+    for _ in range(200):
+        info = aug.step(rgb, np.array([2000]))
+    assert not info.fg[0]
+    before = [a.copy() for a in aug.get_state()]
+    info = aug.step(rgb, np.array([0]))
+    assert info.hole[0] and not info.fg[0]
+    for a, b in zip(aug.get_state(), before):
+        np.testing.assert_array_equal(a, b)
+    info = aug.step(rgb, np.array([1600]))
+    assert info.fg[0] and not info.matched[0]
