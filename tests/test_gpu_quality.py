@@ -76,3 +76,47 @@ def test_quality_over_illumination_ramp():
     assert rep["ramp_clip"]["rgb"]["ramp"] < rep["constant_gain"]["rgb"]["ramp"] - 0.05
     # ... and the fused mask keeps more of it than colour alone
     assert rep["ramp_clip"]["fused"]["ramp"] > rep["ramp_clip"]["rgb"]["ramp"]
+
+
+def _variant_f1(spec, **seg_kw):
+    """Per-frame F1 of one model configuration over the 300-frame clip."""
+    st = Stream(spec)
+    n = spec.npix
+    seg = Segmenter(spec.width, spec.height, GMM_RGB | GMM_DEPTH, 5, **seg_kw)
+    out = {}
+    try:
+        for t in range(300):
+            rgb, dep = st.rgb(t, device=DEV), st.depth(t, device=DEV)
+            truth = pack_mask(st.truth(t, device=DEV))
+            if seg.augmented:
+                masks = {"augmented": seg.apply_augmented(rgb, dep)}
+            else:
+                fr, fd, ff = seg.apply_fused(rgb, dep)
+                masks = {"rgb": fr, "depth": fd, "fused": ff}
+            for name, words in masks.items():
+                out.setdefault(name, []).append(confusion(words, truth, n).f1)
+    finally:
+        seg.close()
+    return out
+
+
+def test_ablations_over_illumination_ramp():
+    """The variants the paper argues against, on the clip with the gain ramp: the four-channel
+    augmentation (Sec. III.B) and Stauffer-Grimson's density rate for the mean and variance.
+    The paper's claim for the augmentation: it keeps the colour model's artefacts, so under the
+    illumination change it does no better than colour alone and worse than the fused mask."""
+    wl = workload("plain-640x480")
+    spec = wl.streams[0]
+    win = {"before": (20, 100), "ramp": (100, 151), "after": (160, 300)}
+    series = {"method": _variant_f1(spec), "augmented": _variant_f1(spec, augmented=True),
+              "density_rate": _variant_f1(spec, rho="density")}
+    rep = {tag: {k: {w: float(np.nanmean(v[a:b])) for w, (a, b) in win.items()} for k, v in f1.items()}
+           for tag, f1 in series.items()}
+    print("ABLATION_REPORT " + json.dumps(rep), flush=True)
+    sys.stdout.flush()
+    aug = rep["augmented"]["augmented"]["ramp"]
+    assert aug < rep["method"]["fused"]["ramp"] - 0.1
+    assert aug < rep["method"]["depth"]["ramp"] - 0.1
+    for tag in rep:
+        for k in rep[tag]:
+            assert all(np.isfinite(list(rep[tag][k].values()))), (tag, k)
