@@ -202,6 +202,22 @@ __host__ __device__ constexpr uint32_t prefix_bytes() {
   return chunks * 64u * kChunkBytes + singles * 64u * es;
 }
 
+// Whether load_values<NV, LIMIT, S> reads value v: its whole 16-byte chunk comes along when the
+// chunk starts below LIMIT, so a chunk may carry values at or beyond LIMIT.
+template <int NV, int LIMIT, typename S>
+__host__ __device__ constexpr bool value_read(uint32_t v) {
+  constexpr uint32_t vpc = kChunkBytes / sizeof(S), nf = (NV / vpc) * vpc;
+  return v < nf ? (v / vpc) * vpc < static_cast<uint32_t>(LIMIT) : v < static_cast<uint32_t>(LIMIT);
+}
+
+// Every value a store of [0, SF) writes (whole chunks) is one a load of [0, LF) read.
+template <int NV, int LF, int SF, typename S>
+__host__ __device__ constexpr bool stores_only_read() {
+  for (uint32_t v = 0; v < static_cast<uint32_t>(NV); ++v)
+    if (value_read<NV, SF, S>(v) && !value_read<NV, LF, S>(v)) return false;
+  return true;
+}
+
 // Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
 // it: all weights, rank 0 (variance, means) and the variance of rank 1.
 template <int M, int C>
@@ -220,8 +236,9 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
   for (int r = 0; r < M; ++r) {
 #pragma unroll
     for (int c = 0; c < C; ++c) m.mu[c][r] = v[value_index(c, r, M, C)];
-    // a variance not read stays at 1: any use of it is discarded by the caller
-    m.var[r] = value_index(C, r, M, C) < static_cast<uint32_t>(LIMIT) ? v[value_index(C, r, M, C)] : 1.f;
+    // a variance not read stays at 1 (any use of it is discarded by the caller); one that came
+    // along in a chunk keeps its value, since the chunk is written back whole
+    m.var[r] = value_read<(C + 2) * M, LIMIT, S>(value_index(C, r, M, C)) ? v[value_index(C, r, M, C)] : 1.f;
     m.w[r] = v[value_index(C + 1, r, M, C)];
   }
 }

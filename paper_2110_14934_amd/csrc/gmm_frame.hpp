@@ -63,6 +63,7 @@ __device__ __forceinline__ bool step_modality(const StateBlock& blk, uint32_t p,
   constexpr int NV = (C + 2) * M;
   constexpr int LF = kFastLoad<M, C>;
   constexpr int SF = kFastStore<M, C>;
+  static_assert(stores_only_read<NV, LF, SF, S>(), "the fast path writes back a value it did not read");
   Mix<M, C> m;
   bool fg = false;
   int j = 0, q = 0;
