@@ -167,9 +167,10 @@ const char* gmm_last_error(void);
 /*
  * Measurement aid: when `wave_bytes` is a device array of ceil(width*height/64) uint64, every
  * later launch on this handle (plain or batched) ADDS to entry i the bytes of mixture state that
- * wave i (pixels 64i..64i+63) read and wrote. The traffic of a frame depends on the data: a wave
- * whose pixels all match their top-ranked component and keep it moves only the weights and that
- * component. NULL stops recording. The caller owns (and zeroes) the array.
+ * wave i (pixels 64i..64i+63) read and wrote. The traffic of a frame depends on the data: a
+ * pixel that matches its top-ranked component and keeps it moves only the weights and that
+ * component (and reads the second rank's variance); any other pixel reads and writes its whole
+ * state. NULL stops recording. The caller owns (and zeroes) the array.
  */
 gmm_status gmm_set_traffic_record(gmm_handle* h, uint64_t* wave_bytes);
 

@@ -47,38 +47,42 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
   return static_cast<float>(row[xx]);
 }
 
-// One modality of pixel p, with lazy state traffic. First only the values a frame needs when
-// the pixel matches its rank-0 component and that component keeps its rank are read (all
-// weights, rank 0, rank 1's variance), and the step is run on them. If every active lane of the
-// wave took that path, only the weights and rank 0 are written back. Otherwise the wave reads
-// the whole state and runs the step again from the original values, then writes everything.
-// The step itself never depends on which path ran (the re-sort stops at the first neighbour it
-// may not pass, rank 1 here), so results are the same either way. `valid` lanes hold a pixel;
-// `active` lanes update it (a depth hole is valid but not active: it writes back what it read,
-// so every written row is whole). Returns the foreground bit; adds the state bytes this wave
-// moved to `wave_bytes`.
+// One modality of pixel p, with lazy state traffic decided lane by lane. load_prefix reads only
+// the values a frame needs when the pixel matches its rank-0 component and that component keeps
+// its rank (all weights, rank 0, rank 1's variance); step_modality runs the step on them. A lane
+// for which that held writes back only the weights and rank 0. Any other lane reads its whole
+// state, runs the step again from the original values and writes everything. The step never
+// depends on which path ran (the re-sort stops at the first neighbour it may not pass, rank 1
+// here), so results are the same either way. `valid` lanes hold a pixel; `active` lanes update
+// it (a depth hole is valid but not active: it writes back what it read). Returns the
+// foreground bit; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
 template <int M, int C, typename S>
-__device__ __forceinline__ bool step_modality(const StateBlock& blk, uint32_t p, bool valid, bool active,
-                                              const float (&x)[C], const ModelConsts& k, uint32_t& wave_bytes) {
+__device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid) {
+  if (valid) load_mix<M, C, S, kFastLoad<M, C>>(m, blk, p);
+}
+
+template <int M, int C, typename S>
+__device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
+                                              bool active, const float (&x)[C], const ModelConsts& k,
+                                              uint32_t& wave_bytes) {
   constexpr int NV = (C + 2) * M;
   constexpr int LF = kFastLoad<M, C>;
   constexpr int SF = kFastStore<M, C>;
   static_assert(stores_only_read<NV, LF, SF, S>(), "the fast path writes back a value it did not read");
-  Mix<M, C> m;
   bool fg = false;
   int j = 0, q = 0;
-  if (valid) load_mix<M, C, S, LF>(m, blk, p);
   if (active) fg = mix_step<M, C>(m, x, k, j, q);
   const bool slow = active && (j != 0 || q != 0);
-  if (__ballot(slow) == 0) {
-    if (valid) store_mix<M, C, S, SF>(m, blk, p);
-    wave_bytes += prefix_bytes<NV, LF, S>() + prefix_bytes<NV, SF, S>();
-  } else {
-    if (valid) load_mix<M, C, S, NV>(m, blk, p);
-    if (active) fg = mix_step<M, C>(m, x, k, j, q);
-    if (valid) store_mix<M, C, S, NV>(m, blk, p);
-    wave_bytes += 2 * prefix_bytes<NV, NV, S>();
+  if (slow) {
+    load_mix<M, C, S, NV>(m, blk, p);
+    fg = mix_step<M, C>(m, x, k, j, q);
+    store_mix<M, C, S, NV>(m, blk, p);
+  } else if (valid) {
+    store_mix<M, C, S, SF>(m, blk, p);
   }
+  const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
+  wave_bytes += (n_valid - n_slow) * ((prefix_bytes<NV, LF, S>() + prefix_bytes<NV, SF, S>()) / kWave) +
+                n_slow * (2u * prefix_bytes<NV, NV, S>() / kWave);
   return fg;
 }
 
@@ -100,7 +104,9 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     const bool active = valid && !(a.kc.hole_skip && d == 0u);
     const float x[4] = {x3[0], x3[1], x3[2], static_cast<float>(min(d >> 4, 255u))};
     const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 6 * M);
-    const bool fg = step_modality<M, 4, S>(blk, p, valid, active, x, a.kc, wave_bytes);
+    Mix<M, 4> m;
+    load_prefix<M, 4, S>(m, blk, p, valid);
+    const bool fg = step_modality<M, 4, S>(m, blk, p, valid, active, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fg);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
@@ -108,7 +114,9 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     float x[3];
     load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);
     const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
-    fgc = step_modality<M, 3, S>(blk, p, valid, valid, x, a.kc, wave_bytes);
+    Mix<M, 3> m;
+    load_prefix<M, 3, S>(m, blk, p, valid);
+    fgc = step_modality<M, 3, S>(m, blk, p, valid, valid, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fgc);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
@@ -116,8 +124,10 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     const float xd = valid ? load_depth_pixel(a, p) : 0.f;
     const bool active = valid && !(a.kd.hole_skip && xd == 0.f);
     const StateBlock blk = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
+    Mix<M, 1> m;
+    load_prefix<M, 1, S>(m, blk, p, valid);
     const float x1[1] = {xd};
-    fgd = step_modality<M, 1, S>(blk, p, valid, active, x1, a.kd, wave_bytes);
+    fgd = step_modality<M, 1, S>(m, blk, p, valid, active, x1, a.kd, wave_bytes);
     const uint64_t bits = __ballot(fgd);
     if (lane == 0 && valid) a.fg_depth[wave_base >> 6] = bits;
   }

@@ -408,11 +408,13 @@ def test_error_paths_on_device():
         seg.close()
 
 
-def test_traffic_record_counts_fast_and_full_waves():
-    """Frame 0 matches nothing (every wave reads and writes the whole state: 2 x 40 values x 64
-    lanes x 4 B = 20480 B per wave); the same frame again matches rank 0 everywhere and keeps the
-    order, so every wave moves only the weights and rank 0 (+ rank 1's variance on the read side):
-    colour 3 + 3 chunks, depth 2 + 2 chunks of 1 KB = 10240 B."""
+def test_traffic_record_counts_fast_and_full_lanes():
+    """Traffic is decided per lane. Frame 0 matches nothing: every colour lane reads and writes its
+    whole state (2 x 25 values x 4 B = 200 B), every depth lane with a reading too (2 x 15 x 4 B =
+    120 B), while a depth hole moves only the prefix (2 chunks read, 2 written: 64 B). The same
+    frame again matches rank 0 everywhere and keeps the order, so every lane moves only the
+    weights and rank 0 (+ rank 1's variance on the read side): colour 3 + 3 chunks of 16 B = 96 B,
+    depth 2 + 2 chunks = 64 B, 10240 B per wave."""
     spec = StreamSpec(160, 120, n_boxes=1, box_min=20, box_max=20, hole_p=0.05, seed=61)
     st = Stream(spec)
     seg = Segmenter(160, 120, GMM_RGB | GMM_DEPTH, 5)
@@ -420,15 +422,18 @@ def test_traffic_record_counts_fast_and_full_waves():
     try:
         _abi.gmm_set_traffic_record(seg.handle, rec)
         rgb, depth = st.rgb(0, device=DEV), st.depth(0, device=DEV)
+        holes = (depth.reshape(-1, 64) == 0).sum(dim=1).to(torch.int64)
+        assert int(holes.sum()) > 0
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        assert torch.all(rec == 20480)
+        first = 64 * 200 + (64 - holes) * 120 + holes * 64
+        assert torch.equal(rec, first)
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        assert torch.all(rec == 20480 + 10240)
+        assert torch.equal(rec, first + 10240)
         _abi.gmm_set_traffic_record(seg.handle, None)
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        assert torch.all(rec == 30720)
+        assert torch.equal(rec, first + 10240)
     finally:
         seg.close()
