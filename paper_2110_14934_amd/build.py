@@ -21,6 +21,12 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # fp32 denormals are kept (IEEE behaviour), fused multiply-add is allowed
     "-fno-gpu-flush-denormals-to-zero", "-ffp-contract=fast",
+    # the per-pixel mixture must live in registers. The vector-combine pass widens a scalar read
+    # of a mixture field (in a helper optimised before it is inlined) into a 16-byte vector
+    # read; after inlining that read spans several fields, the mixture can no longer be split
+    # into registers and the backend moves it to LDS (~7-20 KB per block, an LDS round trip
+    # per access). Without the pass every frame kernel keeps only its 768-byte RGB staging.
+    "-mllvm", "-disable-vector-combine",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
 

@@ -10,7 +10,31 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rgbd {
+
+// Compile-time loop: f(std::integral_constant<int, I>{}) for I = B .. E-1. The per-pixel code
+// indexes its arrays only through such constants, so every index is fixed before any
+// optimisation runs and the whole mixture stays in registers. (With ordinary unrolled loops the
+// compiler may turn "a ? v[r-1] : v[r]" into a load from a selected address before the loop is
+// unrolled; the array then needs memory and lands in LDS, one round trip per access.)
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+#define RGBD_I(i_) decltype(i_)::value
+// loop bodies are inlined before any other optimisation sees them (see static_for)
+#define RGBD_BODY __attribute__((always_inline))
+
+// c ? a : b on values. (A conditional whose operands are both lvalues - two array elements, or
+// an element and a local - is itself an lvalue: it selects an address and loads from it, which
+// keeps the arrays in memory. Passing by value selects the values.)
+__device__ __forceinline__ float pick(bool c, float a, float b) { return c ? a : b; }
+__device__ __forceinline__ int pick(bool c, int a, int b) { return c ? a : b; }
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
@@ -120,7 +144,9 @@ template <> struct BufIO<float> {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.rsrc, off, 0, 0);
   }
   static __device__ __forceinline__ float from_word(uint32_t w, int) { return __builtin_bit_cast(float, w); }
-  static __device__ __forceinline__ uint32_t word(const float* v) { return __builtin_bit_cast(uint32_t, v[0]); }
+  // the 32-bit word holding value a (and b, for 16-bit types, in the high half); by value, so
+  // the values stay in registers
+  static __device__ __forceinline__ uint32_t word(float a, float) { return __builtin_bit_cast(uint32_t, a); }
 };
 template <> struct BufIO<f16s> {
   static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
@@ -133,8 +159,8 @@ template <> struct BufIO<f16s> {
   static __device__ __forceinline__ float from_word(uint32_t w, int half) {
     return Storage<f16s>::load(f16s{static_cast<uint16_t>(half ? (w >> 16) : (w & 0xFFFFu))});
   }
-  static __device__ __forceinline__ uint32_t word(const float* v) {
-    return static_cast<uint32_t>(Storage<f16s>::pack(v[0]).b) | (static_cast<uint32_t>(Storage<f16s>::pack(v[1]).b) << 16);
+  static __device__ __forceinline__ uint32_t word(float a, float b) {
+    return static_cast<uint32_t>(Storage<f16s>::pack(a).b) | (static_cast<uint32_t>(Storage<f16s>::pack(b).b) << 16);
   }
 };
 template <> struct BufIO<bf16s> {
@@ -147,47 +173,10 @@ template <> struct BufIO<bf16s> {
   static __device__ __forceinline__ float from_word(uint32_t w, int half) {
     return __builtin_bit_cast(float, half ? (w & 0xFFFF0000u) : (w << 16));
   }
-  static __device__ __forceinline__ uint32_t word(const float* v) {
-    return static_cast<uint32_t>(Storage<bf16s>::pack(v[0]).b) | (static_cast<uint32_t>(Storage<bf16s>::pack(v[1]).b) << 16);
+  static __device__ __forceinline__ uint32_t word(float a, float b) {
+    return static_cast<uint32_t>(Storage<bf16s>::pack(a).b) | (static_cast<uint32_t>(Storage<bf16s>::pack(b).b) << 16);
   }
 };
-
-// Values [0, LIMIT) of pixel p: every 16-byte chunk and single value that starts below LIMIT
-// (whole chunks, so a little beyond LIMIT may come along). LIMIT = NV reads everything.
-template <int NV, int LIMIT, typename S>
-__device__ __forceinline__ void load_values(float (&v)[NV], const StateBlock& b, uint32_t p) {
-  constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc, vpw = 4 / es;
-  const uint32_t lane = p & 63u;
-  const uint32_t base = (p >> 6) * b.tile_bytes;
-#pragma unroll
-  for (uint32_t c = 0; c < nc; ++c) {
-    if (c * vpc >= static_cast<uint32_t>(LIMIT)) break;
-    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
-#pragma unroll
-    for (uint32_t i = 0; i < vpc; ++i) v[c * vpc + i] = BufIO<S>::from_word(w[i / vpw], static_cast<int>(i % vpw));
-  }
-#pragma unroll
-  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j)
-    if (j < static_cast<uint32_t>(LIMIT)) v[j] = BufIO<S>::ld(b, base + tile_value_offset(j, lane, NV, es));
-}
-
-template <int NV, int LIMIT, typename S>
-__device__ __forceinline__ void store_values(const float (&v)[NV], const StateBlock& b, uint32_t p) {
-  constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc, vpw = 4 / es;
-  const uint32_t lane = p & 63u;
-  const uint32_t base = (p >> 6) * b.tile_bytes;
-#pragma unroll
-  for (uint32_t c = 0; c < nc; ++c) {
-    if (c * vpc >= static_cast<uint32_t>(LIMIT)) break;
-    u32x4 w;
-#pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) w[i] = BufIO<S>::word(&v[c * vpc + i * vpw]);
-    __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
-  }
-#pragma unroll
-  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j)
-    if (j < static_cast<uint32_t>(LIMIT)) BufIO<S>::st(b, base + tile_value_offset(j, lane, NV, es), v[j]);
-}
 
 // Bytes of state one wave moves when it reads (or writes) values [0, LIMIT): whole chunks and
 // single rows that start below LIMIT, for all 64 lanes.
@@ -226,34 +215,76 @@ constexpr int kFastLoad = M > 1 ? M + (C + 1) + 1 : M + (C + 1);
 template <int M, int C>
 constexpr int kFastStore = M + (C + 1);
 
-template <int M, int C, typename S, int LIMIT = (C + 2) * M>
-__device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  float v[(C + 2) * M];
-#pragma unroll
-  for (int i = 0; i < (C + 2) * M; ++i) v[i] = 0.f;
-  load_values<(C + 2) * M, LIMIT, S>(v, b, p);
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) m.mu[c][r] = v[value_index(c, r, M, C)];
-    // a variance not read stays at 1 (any use of it is discarded by the caller); one that came
-    // along in a chunk keeps its value, since the chunk is written back whole
-    m.var[r] = value_read<(C + 2) * M, LIMIT, S>(value_index(C, r, M, C)) ? v[value_index(C, r, M, C)] : 1.f;
-    m.w[r] = v[value_index(C + 1, r, M, C)];
+// Value V (in value_index order) of a pixel's mixture, as the Mix field that holds it.
+template <int M, int C, int V>
+__device__ __forceinline__ float& field(Mix<M, C>& m) {
+  if constexpr (V < M) {
+    return m.w[V];
+  } else {
+    constexpr int r = (V - M) / (C + 1), pos = (V - M) % (C + 1);
+    if constexpr (pos == 0) return m.var[r];
+    else return m.mu[pos - 1][r];
   }
 }
+template <int M, int C, int V>
+__device__ __forceinline__ float field(const Mix<M, C>& m) {
+  return field<M, C, V>(const_cast<Mix<M, C>&>(m));
+}
 
+// Values [0, LIMIT) of pixel p, straight into the Mix: every 16-byte chunk and single value
+// that starts below LIMIT (whole chunks, so a little beyond LIMIT may come along; see
+// value_read). A value not read is left at 0 - a variance at 1, so that keys stay finite (any
+// use of it is discarded by the caller). LIMIT = NV reads everything.
+template <int M, int C, typename S, int LIMIT = (C + 2) * M>
+__device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+  constexpr int NV = (C + 2) * M, es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc,
+                vpw = 4 / es;
+  const uint32_t lane = p & 63u;
+  const uint32_t base = (p >> 6) * b.tile_bytes;
+  static_for<0, NV>([&](auto v_) RGBD_BODY {
+    constexpr int v = RGBD_I(v_);
+    if constexpr (!value_read<NV, LIMIT, S>(v)) field<M, C, v>(m) = (v >= M && (v - M) % (C + 1) == 0) ? 1.f : 0.f;
+  });
+  static_for<0, nc>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    if constexpr (c * vpc < LIMIT) {
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
+      static_for<0, vpc>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        field<M, C, c * vpc + i>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
+      });
+    }
+  });
+  static_for<nf, NV>([&](auto j_) RGBD_BODY {
+    constexpr int j = RGBD_I(j_);
+    if constexpr (j < LIMIT) field<M, C, j>(m) = BufIO<S>::ld(b, base + tile_value_offset(j, lane, NV, es));
+  });
+}
+
+// Values [0, LIMIT) of pixel p from the Mix (whole chunks, as load_mix reads them).
 template <int M, int C, typename S, int LIMIT = (C + 2) * M>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  float v[(C + 2) * M];
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) v[value_index(c, r, M, C)] = m.mu[c][r];
-    v[value_index(C, r, M, C)] = m.var[r];
-    v[value_index(C + 1, r, M, C)] = m.w[r];
-  }
-  store_values<(C + 2) * M, LIMIT, S>(v, b, p);
+  constexpr int NV = (C + 2) * M, es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc,
+                vpw = 4 / es;
+  const uint32_t lane = p & 63u;
+  const uint32_t base = (p >> 6) * b.tile_bytes;
+  static_for<0, nc>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    if constexpr (c * vpc < LIMIT) {
+      // a zero (not undefined) start: element 0 is then never widened into a 16-byte load
+      // from the mixture, which would pin the mixture in memory
+      u32x4 w = {0u, 0u, 0u, 0u};
+      static_for<0, 4>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        w[i] = BufIO<S>::word(field<M, C, c * vpc + i * vpw>(m), field<M, C, c * vpc + i * vpw + vpw - 1>(m));
+      });
+      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
+    }
+  });
+  static_for<nf, NV>([&](auto j_) RGBD_BODY {
+    constexpr int j = RGBD_I(j_);
+    if constexpr (j < LIMIT) BufIO<S>::st(b, base + tile_value_offset(j, lane, NV, es), field<M, C, j>(m));
+  });
 }
 
 // One frame of the mixture model for one pixel (Sec. III.A with the update rules of the
@@ -278,129 +309,126 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
   // match, in rank order
   int j = M;
   float d2j = 0.f;  // squared distance to the matched component
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
+  static_for<0, M>([&](auto r_) RGBD_BODY {
+    constexpr int r = RGBD_I(r_);
     float d2 = 0.f;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
       const float t = x[c] - s.mu[c][r];
       d2 = fmaf(t, t, d2);
-    }
+    });
     const bool hit = (s.w[r] > 0.f) & (d2 < k.k2 * s.var[r]);  // no short-circuit: no branch
     const bool take = (j == M) & hit;
-    d2j = take ? d2 : d2j;
-    j = take ? r : j;
-  }
+    d2j = pick(take, d2, d2j);
+    j = pick(take, r, j);
+  });
   const bool matched = j < M;
   const int t = matched ? j : M - 1;
 
   // the changed component: gathered, updated once (branch-free selects over the ranks)
   float mj[C], vj = s.var[0], wj = s.w[0];
-#pragma unroll
-  for (int c = 0; c < C; ++c) mj[c] = s.mu[c][0];
-#pragma unroll
-  for (int r = 1; r < M; ++r) {
+  static_for<0, C>([&](auto c_) RGBD_BODY { mj[RGBD_I(c_)] = s.mu[RGBD_I(c_)][0]; });
+  static_for<1, M>([&](auto r_) RGBD_BODY {
+    constexpr int r = RGBD_I(r_);
     const bool isj = (r == j);
-    vj = isj ? s.var[r] : vj;
-    wj = isj ? s.w[r] : wj;
-#pragma unroll
-    for (int c = 0; c < C; ++c) mj[c] = isj ? s.mu[c][r] : mj[c];
-  }
+    vj = pick(isj, s.var[r], vj);
+    wj = pick(isj, s.w[r], wj);
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
+      mj[c] = pick(isj, s.mu[c][r], mj[c]);
+    });
+  });
   float d2n = 0.f;
   if (k.rho_density) {  // uniform over the wave
     // rho = alpha (2 pi var)^(-C/2) exp(-d2 / (2 var)), with exp(y) = 2^(y log2 e); the
     // update is written as an increment, which keeps a rate of 1e-5 from drowning in rounding
     const float rv = __builtin_amdgcn_rcpf(vj);
     float dens = (C & 1) ? __builtin_amdgcn_rsqf(vj) : 1.f;
-#pragma unroll
-    for (int c = 0; c < C / 2; ++c) dens *= rv;
+    static_for<0, C / 2>([&](auto) RGBD_BODY { dens *= rv; });
     const float rho = k.rho_scale * dens * __builtin_amdgcn_exp2f(-0.72134752f * d2j * rv);  // -log2(e)/2
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
       mj[c] = fmaf(rho, x[c] - mj[c], mj[c]);
       const float tt = x[c] - mj[c];
       d2n = fmaf(tt, tt, d2n);
-    }
+    });
     vj = fmaxf(k.var_min, fmaf(rho, d2n - vj, vj));
   } else {
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
       mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
       const float tt = x[c] - mj[c];
       d2n = fmaf(tt, tt, d2n);
-    }
+    });
     vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
   }
   wj = fmaf(k.oma, wj, k.alpha);
   // no match: the least probable (last-ranked) component is replaced
-  float tmu[C], tvar, tw;
-#pragma unroll
-  for (int c = 0; c < C; ++c) tmu[c] = matched ? mj[c] : x[c];
-  tvar = matched ? vj : k.var0;
-  tw = matched ? wj : k.w_init;
+  float tmu[C];
+  static_for<0, C>([&](auto c_) RGBD_BODY { tmu[RGBD_I(c_)] = pick(matched, mj[RGBD_I(c_)], x[RGBD_I(c_)]); });
+  const float tvar = pick(matched, vj, k.var0);
+  float tw = pick(matched, wj, k.w_init);
 
   // decay of the other weights, renormalisation of all
   float w[M];
   float S = 0.f;
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-    w[r] = (r == t) ? tw : k.oma * s.w[r];
+  static_for<0, M>([&](auto r_) RGBD_BODY {
+    constexpr int r = RGBD_I(r_);
+    w[r] = pick(r == t, tw, k.oma * s.w[r]);
     S += w[r];
-  }
+  });
   const float inv = 1.0f / S;
-#pragma unroll
-  for (int r = 0; r < M; ++r) w[r] *= inv;
+  static_for<0, M>([&](auto r_) RGBD_BODY { w[RGBD_I(r_)] *= inv; });
   tw = tw * inv;
 
   // re-sort: walk the changed component to its place
   const float kt = tw * __builtin_amdgcn_rsqf(tvar);
   float key[M];
-#pragma unroll
-  for (int r = 0; r < M; ++r) key[r] = w[r] * __builtin_amdgcn_rsqf(s.var[r]);
+  static_for<0, M>([&](auto r_) RGBD_BODY { key[RGBD_I(r_)] = w[RGBD_I(r_)] * __builtin_amdgcn_rsqf(s.var[RGBD_I(r_)]); });
   int down = 0, up = 0;
   bool go_down = true, go_up = true;
-#pragma unroll
-  for (int r = 1; r < M; ++r) {  // ranks below t, nearest first
+  static_for<1, M>([&](auto r_) RGBD_BODY {  // ranks below t, nearest first
+    constexpr int r = RGBD_I(r_);
     const bool below = r > t;
     go_down = go_down & (!below | (key[r] > kt));
     down += (below & go_down) ? 1 : 0;
-  }
-#pragma unroll
-  for (int r = M - 2; r >= 0; --r) {  // ranks above t, nearest first
+  });
+  static_for<0, M - 1>([&](auto i_) RGBD_BODY {  // ranks above t, nearest first
+    constexpr int r = M - 2 - RGBD_I(i_);
     const bool above = r < t;
     go_up = go_up & (!above | (key[r] < kt));
     up += (above & go_up) ? 1 : 0;
-  }
+  });
   const int q = t + down - up;
 
   // rank o takes: the changed component at q; above q the old rank o (or o+1 once past t);
   // below q the old rank o (or o-1 once past t)
   Mix<M, C> o;
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
+  static_for<0, M>([&](auto r_) RGBD_BODY {
+    constexpr int r = RGBD_I(r_);
+    constexpr int rp = r > 0 ? r - 1 : 0, rn = r < M - 1 ? r + 1 : M - 1;
     const int src = r < q ? (r < t ? r : r + 1) : (r > t ? r : r - 1);
     const bool from_prev = src == r - 1, from_next = src == r + 1;
-    const int rp = r > 0 ? r - 1 : 0, rn = r < M - 1 ? r + 1 : M - 1;
-    float v = from_prev ? s.var[rp] : (from_next ? s.var[rn] : s.var[r]);
-    float ww = from_prev ? w[rp] : (from_next ? w[rn] : w[r]);
-    o.var[r] = (r == q) ? tvar : v;
-    o.w[r] = (r == q) ? tw : ww;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const float mv = from_prev ? s.mu[c][rp] : (from_next ? s.mu[c][rn] : s.mu[c][r]);
-      o.mu[c][r] = (r == q) ? tmu[c] : mv;
-    }
-  }
+    const float v = pick(from_prev, s.var[rp], pick(from_next, s.var[rn], s.var[r]));
+    const float ww = pick(from_prev, w[rp], pick(from_next, w[rn], w[r]));
+    o.var[r] = pick(r == q, tvar, v);
+    o.w[r] = pick(r == q, tw, ww);
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
+      const float mv = pick(from_prev, s.mu[c][rp], pick(from_next, s.mu[c][rn], s.mu[c][r]));
+      o.mu[c][r] = pick(r == q, tmu[c], mv);
+    });
+  });
   s = o;
 
   // background set: the first B ranks whose cumulative weight exceeds T
   int B = M;
   float run = 0.f;
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
+  static_for<0, M>([&](auto r_) RGBD_BODY {
+    constexpr int r = RGBD_I(r_);
     run += s.w[r];
     B = (B == M && run > k.T) ? r + 1 : B;
-  }
+  });
   j_out = j;
   q_out = q;
   return !matched || q >= B;
