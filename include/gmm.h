@@ -262,10 +262,11 @@ gmm_status gmm_batch_run(gmm_batch* b, int32_t slot, void* stream);
 gmm_status gmm_batch_apply(gmm_batch* b, const gmm_stream_io* io, void* stream);
 
 /*
- * Choose the launch shape by timing trial launches of slot `slot` over block_threads {256, 512}
- * x tile multiples {1, 2, 4, 8, 16} x blocks_per_cu {2, 4, 8, 16}, keep the fastest, and cache
- * it for this process per (device, M, state dtype, multiset of stream shapes and modalities).
- * Every stream's state is saved first and restored afterwards (the slot's masks are
+ * Choose the launch shape by timing trial launches over block_threads {256, 512} x tile
+ * multiples {1, 2, 4, 8, 16} x blocks_per_cu {2, 4, 8, 16}, keep the fastest, and cache it for
+ * this process per (device, M, state dtype, multiset of stream shapes and modalities). Each
+ * candidate runs slot `slot` and up to three more prepared slots after it, in order, from the
+ * same saved state. Every stream's state is restored afterwards (the slots' masks are
  * overwritten by the trials). Synchronous. Reports the winner and its time per launch.
  */
 gmm_status gmm_batch_autotune(gmm_batch* b, int32_t slot, void* stream, gmm_batch_tuning* best,

@@ -396,6 +396,14 @@ gmm_status gmm_batch_autotune(gmm_batch* b, int32_t slot, void* stream, gmm_batc
   gmm_batch_tuning best = start;
   double best_ms = 1e30;
   gmm_status st = GMM_OK;
+  // every candidate is timed from the same saved state on the same frame-sets (`slot` and the
+  // prepared slots after it, cyclically), so all see the same mix of pixels that keep their
+  // top component and pixels that do not
+  std::vector<int32_t> slots;
+  for (int32_t i = 0; i < b->n_slots && slots.size() < 4; ++i) {
+    const int32_t sl = (slot + i) % b->n_slots;
+    if (b->slot_ready[sl]) slots.push_back(sl);
+  }
   if (e == hipSuccess) {
     const int blocks[] = {256, 512};
     const int tile_mult[] = {1, 2, 4, 8, 16};
@@ -407,10 +415,12 @@ gmm_status gmm_batch_autotune(gmm_batch* b, int32_t slot, void* stream, gmm_batc
           st = apply_tuning(b, t);
           if (st != GMM_OK) break;
           e = run_slot(b, slot, hs);  // warm-up
+          if (e == hipSuccess) e = copy_states(false);
           if (e == hipSuccess) e = hipEventRecord(e0, hs);
-          const int reps = 3;
-          for (int r = 0; r < reps && e == hipSuccess; ++r) e = run_slot(b, slot, hs);
+          const int reps = static_cast<int>(slots.size());
+          for (int r = 0; r < reps && e == hipSuccess; ++r) e = run_slot(b, slots[r], hs);
           if (e == hipSuccess) e = hipEventRecord(e1, hs);
+          if (e == hipSuccess) e = copy_states(false);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.f;
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
