@@ -98,43 +98,49 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   bool fgc = false, fgd = false;
   uint32_t wave_bytes = 0;
   if (AUG && (mode & kModeAug) != 0) {
-    float x3[3];
-    load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x3);
-    const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
-    const bool active = valid && !(a.kc.hole_skip && d == 0u);
-    const float x[4] = {x3[0], x3[1], x3[2], static_cast<float>(min(d >> 4, 255u))};
     const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 6 * M);
     Mix<M, 4> m;
     load_prefix<M, 4, S>(m, blk, p, valid);
+    const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
+    float x3[3];
+    load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x3);
+    const bool active = valid && !(a.kc.hole_skip && d == 0u);
+    const float x[4] = {x3[0], x3[1], x3[2], static_cast<float>(min(d >> 4, 255u))};
     const bool fg = step_modality<M, 4, S>(m, blk, p, valid, active, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fg);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
-  if ((mode & kModeRGB) != 0) {
-    float x[3];
-    load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);
-    const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
-    Mix<M, 3> m;
-    load_prefix<M, 3, S>(m, blk, p, valid);
-    fgc = step_modality<M, 3, S>(m, blk, p, valid, valid, x, a.kc, wave_bytes);
+  const bool do_c = (mode & kModeRGB) != 0, do_d = (mode & kModeDepth) != 0, do_f = (mode & kModeFuse) != 0;
+  const StateBlock blk_c = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
+  const StateBlock blk_d = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
+  Mix<M, 3> mc;
+  Mix<M, 1> md;
+  float xd = 0.f;
+  uint32_t fst = 0;
+  // every load of the pixel is issued before any result is used (the state blocks, the fusion
+  // bytes and the frames do not overlap), so a wave waits for memory once, not once per step
+  if (do_c) load_prefix<M, 3, S>(mc, blk_c, p, valid);
+  if (do_d) load_prefix<M, 1, S>(md, blk_d, p, valid);
+  if (do_d && valid) xd = load_depth_pixel(a, p);
+  if (do_f && valid) fst = a.fstate[p];
+  float x[3];
+  if (do_c) load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);
+  if (do_c) {
+    fgc = step_modality<M, 3, S>(mc, blk_c, p, valid, valid, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fgc);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
-  if ((mode & kModeDepth) != 0) {
-    const float xd = valid ? load_depth_pixel(a, p) : 0.f;
+  if (do_d) {
     const bool active = valid && !(a.kd.hole_skip && xd == 0.f);
-    const StateBlock blk = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
-    Mix<M, 1> m;
-    load_prefix<M, 1, S>(m, blk, p, valid);
     const float x1[1] = {xd};
-    fgd = step_modality<M, 1, S>(m, blk, p, valid, active, x1, a.kd, wave_bytes);
+    fgd = step_modality<M, 1, S>(md, blk_d, p, valid, active, x1, a.kd, wave_bytes);
     const uint64_t bits = __ballot(fgd);
     if (lane == 0 && valid) a.fg_depth[wave_base >> 6] = bits;
   }
-  if ((mode & kModeFuse) != 0) {
+  if (do_f) {
     bool fgf = false;
     if (valid) {
-      const uint32_t st = fuse_transition(a.fstate[p], fgc, fgd);
+      const uint32_t st = fuse_transition(fst, fgc, fgd);
       a.fstate[p] = static_cast<uint8_t>(st);
       fgf = (st >> 3) & 1u;
     }
