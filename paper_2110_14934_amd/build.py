@@ -19,8 +19,9 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed fp32 instructions stay off; plain fp32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # fp32 denormals are kept (IEEE behaviour), fused multiply-add is allowed
-    "-fno-gpu-flush-denormals-to-zero", "-ffp-contract=fast",
+    # fp32 denormals are kept (IEEE behaviour); fused multiply-add is allowed except where a
+    # "#pragma clang fp contract(off)" asks for separately rounded products and sums
+    "-fno-gpu-flush-denormals-to-zero", "-ffp-contract=fast-honor-pragmas",
     # the per-pixel mixture must live in registers. The vector-combine pass widens a scalar read
     # of a mixture field (in a helper optimised before it is inlined) into a 16-byte vector
     # read; after inlining that read spans several fields, the mixture can no longer be split

@@ -287,6 +287,55 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
   });
 }
 
+// The matched component's new mean, variance and weight (from the values before the update and
+// the squared distance d2j of x to its mean); shared by mix_step and fast_step.
+template <int C>
+__device__ __forceinline__ void update_matched(float (&mj)[C], float& vj, float& wj, float d2j, const float (&x)[C],
+                                               const ModelConsts& k) {
+  float d2n = 0.f;
+  if (k.rho_density) {  // uniform over the wave
+    // rho = alpha (2 pi var)^(-C/2) exp(-d2 / (2 var)), with exp(y) = 2^(y log2 e); the
+    // update is written as an increment, which keeps a rate of 1e-5 from drowning in rounding
+    const float rv = __builtin_amdgcn_rcpf(vj);
+    float dens = (C & 1) ? __builtin_amdgcn_rsqf(vj) : 1.f;
+    static_for<0, C / 2>([&](auto) RGBD_BODY { dens *= rv; });
+    const float rho = k.rho_scale * dens * __builtin_amdgcn_exp2f(-0.72134752f * d2j * rv);  // -log2(e)/2
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
+      mj[c] = fmaf(rho, x[c] - mj[c], mj[c]);
+      const float tt = x[c] - mj[c];
+      d2n = fmaf(tt, tt, d2n);
+    });
+    vj = fmaxf(k.var_min, fmaf(rho, d2n - vj, vj));
+  } else {
+    static_for<0, C>([&](auto c_) RGBD_BODY {
+      constexpr int c = RGBD_I(c_);
+      mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
+      const float tt = x[c] - mj[c];
+      d2n = fmaf(tt, tt, d2n);
+    });
+    vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
+  }
+  wj = fmaf(k.oma, wj, k.alpha);
+}
+
+// Weights after the decay (w_old scaled by 1 - alpha, rank t set to tw), renormalised to sum to
+// one; tw is renormalised with them. Shared by mix_step and fast_step; products and sums are
+// rounded separately (never fused), so both round identically whatever they know of t.
+template <int M>
+__device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const float (&w_old)[M], int t, float oma) {
+  float S = 0.f;
+  static_for<0, M>([&](auto r_) RGBD_BODY {
+#pragma clang fp contract(off)
+    constexpr int r = RGBD_I(r_);
+    w[r] = pick(r == t, tw, oma * w_old[r]);
+    S += w[r];
+  });
+  const float inv = 1.0f / S;
+  static_for<0, M>([&](auto r_) RGBD_BODY { w[RGBD_I(r_)] *= inv; });
+  tw = tw * inv;
+}
+
 // One frame of the mixture model for one pixel (Sec. III.A with the update rules of the
 // paper's reference [6]). Returns the foreground bit; `j_out` is the matched rank (M if none)
 // and `q_out` the rank the updated (or new) component ends up at.
@@ -338,31 +387,7 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       mj[c] = pick(isj, s.mu[c][r], mj[c]);
     });
   });
-  float d2n = 0.f;
-  if (k.rho_density) {  // uniform over the wave
-    // rho = alpha (2 pi var)^(-C/2) exp(-d2 / (2 var)), with exp(y) = 2^(y log2 e); the
-    // update is written as an increment, which keeps a rate of 1e-5 from drowning in rounding
-    const float rv = __builtin_amdgcn_rcpf(vj);
-    float dens = (C & 1) ? __builtin_amdgcn_rsqf(vj) : 1.f;
-    static_for<0, C / 2>([&](auto) RGBD_BODY { dens *= rv; });
-    const float rho = k.rho_scale * dens * __builtin_amdgcn_exp2f(-0.72134752f * d2j * rv);  // -log2(e)/2
-    static_for<0, C>([&](auto c_) RGBD_BODY {
-      constexpr int c = RGBD_I(c_);
-      mj[c] = fmaf(rho, x[c] - mj[c], mj[c]);
-      const float tt = x[c] - mj[c];
-      d2n = fmaf(tt, tt, d2n);
-    });
-    vj = fmaxf(k.var_min, fmaf(rho, d2n - vj, vj));
-  } else {
-    static_for<0, C>([&](auto c_) RGBD_BODY {
-      constexpr int c = RGBD_I(c_);
-      mj[c] = fmaf(k.oma, mj[c], k.alpha * x[c]);
-      const float tt = x[c] - mj[c];
-      d2n = fmaf(tt, tt, d2n);
-    });
-    vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
-  }
-  wj = fmaf(k.oma, wj, k.alpha);
+  update_matched<C>(mj, vj, wj, d2j, x, k);
   // no match: the least probable (last-ranked) component is replaced
   float tmu[C];
   static_for<0, C>([&](auto c_) RGBD_BODY { tmu[RGBD_I(c_)] = pick(matched, mj[RGBD_I(c_)], x[RGBD_I(c_)]); });
@@ -371,15 +396,7 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
 
   // decay of the other weights, renormalisation of all
   float w[M];
-  float S = 0.f;
-  static_for<0, M>([&](auto r_) RGBD_BODY {
-    constexpr int r = RGBD_I(r_);
-    w[r] = pick(r == t, tw, k.oma * s.w[r]);
-    S += w[r];
-  });
-  const float inv = 1.0f / S;
-  static_for<0, M>([&](auto r_) RGBD_BODY { w[RGBD_I(r_)] *= inv; });
-  tw = tw * inv;
+  renormalise<M>(w, tw, s.w, t, k.oma);
 
   // re-sort: walk the changed component to its place
   const float kt = tw * __builtin_amdgcn_rsqf(tvar);
@@ -432,6 +449,36 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
   j_out = j;
   q_out = q;
   return !matched || q >= B;
+}
+
+// The frame of a pixel whose rank-0 component matches x and keeps rank 0, on the values
+// load_prefix reads (all weights, rank 0, rank 1's variance). For such a pixel it computes
+// exactly what mix_step computes (same helpers, same order), far more cheaply: no gather over
+// the ranks, no permutation, and the pixel is background (rank 0 < B, since B >= 1). Returns
+// whether the pixel is such a pixel; if not, `s` holds partial results and the caller runs
+// mix_step on the whole state instead.
+template <int M, int C>
+__device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], const ModelConsts& k) {
+  float d2 = 0.f;
+  static_for<0, C>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    const float t = x[c] - s.mu[c][0];
+    d2 = fmaf(t, t, d2);
+  });
+  const bool hit = (s.w[0] > 0.f) & (d2 < k.k2 * s.var[0]);
+  float mj[C], vj = s.var[0], wj = s.w[0];
+  static_for<0, C>([&](auto c_) RGBD_BODY { mj[RGBD_I(c_)] = s.mu[RGBD_I(c_)][0]; });
+  update_matched<C>(mj, vj, wj, d2, x, k);
+  float w[M];
+  renormalise<M>(w, wj, s.w, 0, k.oma);
+  // rank 0 keeps its place unless rank 1's key is strictly larger
+  bool keeps = true;
+  if constexpr (M > 1) keeps = !(w[1] * __builtin_amdgcn_rsqf(s.var[1]) > wj * __builtin_amdgcn_rsqf(vj));
+  static_for<0, C>([&](auto c_) RGBD_BODY { s.mu[RGBD_I(c_)][0] = mj[RGBD_I(c_)]; });
+  s.var[0] = vj;
+  s.w[0] = wj;
+  static_for<1, M>([&](auto r_) RGBD_BODY { s.w[RGBD_I(r_)] = w[RGBD_I(r_)]; });
+  return hit & keeps;
 }
 
 // List 1 (Sec. III.C): one transition of the fused bit I and counter cpt of a pixel.

@@ -49,11 +49,11 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
 
 // One modality of pixel p, with lazy state traffic decided lane by lane. load_prefix reads only
 // the values a frame needs when the pixel matches its rank-0 component and that component keeps
-// its rank (all weights, rank 0, rank 1's variance); step_modality runs the step on them. A lane
-// for which that held writes back only the weights and rank 0. Any other lane reads its whole
-// state, runs the step again from the original values and writes everything. The step never
-// depends on which path ran (the re-sort stops at the first neighbour it may not pass, rank 1
-// here), so results are the same either way. `valid` lanes hold a pixel; `active` lanes update
+// its rank (all weights, rank 0, rank 1's variance); step_modality runs fast_step, the step
+// specialised to that case, on them. A lane for which that held writes back only the weights
+// and rank 0. Any other lane reads its whole state, runs the full step from the original values
+// and writes everything. fast_step computes exactly what the full step computes for such a
+// pixel, so results never depend on which path ran. `valid` lanes hold a pixel; `active` lanes update
 // it (a depth hole is valid but not active: it writes back what it read). Returns the
 // foreground bit; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
 template <int M, int C, typename S>
@@ -70,11 +70,10 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   constexpr int SF = kFastStore<M, C>;
   static_assert(stores_only_read<NV, LF, SF, S>(), "the fast path writes back a value it did not read");
   bool fg = false;
-  int j = 0, q = 0;
-  if (active) fg = mix_step<M, C>(m, x, k, j, q);
-  const bool slow = active && (j != 0 || q != 0);
+  const bool slow = active && !fast_step<M, C>(m, x, k);
   if (slow) {
     load_mix<M, C, S, NV>(m, blk, p);
+    int j, q;
     fg = mix_step<M, C>(m, x, k, j, q);
     store_mix<M, C, S, NV>(m, blk, p);
   } else if (valid) {
