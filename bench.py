@@ -29,15 +29,16 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_frame_kernel_plain-640x480.json")
 
 
-# the sources the per-frame kernel is compiled from
-FRAME_KERNEL_SOURCES = ("gmm_device.hpp", "gmm_frame.hpp", "gmm_internal.hpp", "gmm_kernels.hip")
+# the sources (and the build script, which holds the compiler flags) of the per-frame kernel
+FRAME_KERNEL_SOURCES = ("csrc/gmm_device.hpp", "csrc/gmm_frame.hpp", "csrc/gmm_internal.hpp",
+                        "csrc/gmm_kernels.hip", "build.py")
 
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2110_14934_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_2110_14934_amd")
     for f in FRAME_KERNEL_SOURCES:
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        h.update(open(os.path.join(pkg, f), "rb").read())
     return h.hexdigest()[:16]
 
 
