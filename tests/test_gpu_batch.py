@@ -64,11 +64,15 @@ def _compare_bitwise(a_segs, b_segs, t):
                 assert torch.equal(x, y), (t, i)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f16"])
-def test_batch_bit_identical_to_single_streams(dtype):
+@pytest.mark.parametrize("dtype,rho", [("f32", "alpha"), ("f16", "alpha"), ("f32", "density")])
+def test_batch_bit_identical_to_single_streams(dtype, rho):
     streams = [Stream(s) for s in SPECS]
-    single = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, **kwargs(MIX)) for s in SPECS]
-    batched = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, **kwargs(MIX)) for s in SPECS]
+    # with the density rate, streams of one batch may mix both rates
+    rhos = [rho if i % 2 == 0 else "alpha" for i in range(len(SPECS))]
+    single = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, rho=r, **kwargs(MIX))
+              for s, r in zip(SPECS, rhos)]
+    batched = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, rho=r, **kwargs(MIX))
+               for s, r in zip(SPECS, rhos)]
     batch = Batch(batched)
     tunings = [(256, 256, 1), (512, 2048, 4), (256, 4096, 16), (512, 512, 2)]
     try:
