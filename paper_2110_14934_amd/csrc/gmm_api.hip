@@ -195,9 +195,11 @@ gmm_status rgbd::new_handle(const gmm_config* cfg, gmm_handle** out) {
   h->npix = static_cast<int64_t>(cfg->width) * cfg->height;
   h->tiles64 = static_cast<uint32_t>((h->npix + kWave - 1) / kWave);
   h->esize = dtype_size(cfg->state_dtype);
-  const size_t plane = static_cast<size_t>(h->tiles64) * kWave * h->esize;  // one plane, all tiles
-  h->rgb_bytes = is_augmented(h) ? plane * 6 * cfg->M : (has_rgb(h) ? plane * 5 * cfg->M : 0);
-  h->depth_bytes = sep_depth(h) ? plane * 3 * cfg->M : 0;
+  const uint32_t M = static_cast<uint32_t>(cfg->M), es = static_cast<uint32_t>(h->esize);
+  const size_t tiles = h->tiles64;
+  h->rgb_bytes = is_augmented(h) ? tiles * tile_layout(M, 4, es).bytes
+                                 : (has_rgb(h) ? tiles * tile_layout(M, 3, es).bytes : 0);
+  h->depth_bytes = sep_depth(h) ? tiles * tile_layout(M, 1, es).bytes : 0;
   h->fuse_bytes = sep_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
   if (std::max(h->rgb_bytes, h->depth_bytes) > 0xFFFFFFFFull) {
     delete h;
@@ -461,7 +463,8 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     const bool present = blk == 0 ? has_rgb(h) : sep_depth(h);
     if (!present) continue;
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
-    const size_t tile_bytes = P * M * kWave * h->esize;
+    const uint32_t C = static_cast<uint32_t>(P - 2);
+    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, static_cast<uint32_t>(h->esize)).bytes;
     // tiled device layout -> canonical [param][rank][pixel]
     const uint32_t nv = static_cast<uint32_t>(P * M);
     for (size_t k = 0; k < P * M; ++k) {
@@ -469,7 +472,8 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
                                      static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
       for (size_t i = 0; i < n; ++i) {
         const size_t at = off + (i / kWave) * tile_bytes +
-                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), nv, static_cast<uint32_t>(h->esize));
+                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), static_cast<uint32_t>(M), C,
+                                            static_cast<uint32_t>(h->esize));
         unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
       }
       o += n;
@@ -501,7 +505,8 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     const bool present = blk == 0 ? has_rgb(h) : sep_depth(h);
     if (!present) continue;
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
-    const size_t tile_bytes = P * M * kWave * h->esize;
+    const uint32_t C = static_cast<uint32_t>(P - 2);
+    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, static_cast<uint32_t>(h->esize)).bytes;
     // canonical [param][rank][pixel] -> tiled device layout
     const uint32_t nv = static_cast<uint32_t>(P * M);
     for (size_t k = 0; k < P * M; ++k) {
@@ -509,7 +514,8 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
                                      static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
       for (size_t i = 0; i < n; ++i) {
         const size_t at = off + (i / kWave) * tile_bytes +
-                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), nv, static_cast<uint32_t>(h->esize));
+                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), static_cast<uint32_t>(M), C,
+                                            static_cast<uint32_t>(h->esize));
         pack_values(in + i, raw.data() + at, 1, h->cfg.state_dtype);
       }
       in += n;

@@ -99,63 +99,84 @@ __host__ __device__ constexpr uint32_t value_index(uint32_t param, uint32_t rank
   return param == C + 1 ? rank : M + rank * (C + 1) + (param == C ? 0 : 1 + param);
 }
 
+// Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
+// it: all weights, rank 0 (variance, means) and the variance of rank 1 ...
+__host__ __device__ constexpr uint32_t fast_load_count(uint32_t M, uint32_t C) {
+  return M > 1 ? M + (C + 1) + 1 : M + (C + 1);
+}
+// ... and the values such a frame changes: all weights and rank 0.
+__host__ __device__ constexpr uint32_t fast_store_count(uint32_t M, uint32_t C) { return M + (C + 1); }
+template <int M, int C>
+constexpr int kFastLoad = static_cast<int>(fast_load_count(M, C));
+template <int M, int C>
+constexpr int kFastStore = static_cast<int>(fast_store_count(M, C));
+
 // One modality's state block as a buffer resource, in a tiled layout. Pixels are grouped in
-// tiles of 64 (one wave); each pixel has NV values (in value_index order). Inside a tile, values
-// are stored in 16-byte chunks per lane: chunk
-// c holds values [c*VPC, (c+1)*VPC) of all 64 lanes as [lane][VPC] (VPC = 16/sizeof(value)), so
-// one wave instruction moves 1 KB of contiguous memory; the NV % VPC values left over are
-// stored as single rows [lane]. A wave's accesses to one modality fall in one contiguous region
-// of NV*64 values, with no padding. A lane's tile + lane byte offset lives in one VGPR and the
-// chunk offsets are compile-time constants, so every state access is one buffer instruction.
-// The range checked by the hardware (num_records) is the whole block: an access outside it
-// reads 0 and drops its write instead of touching other memory. The host keeps every block
-// below 4 GiB.
+// tiles of 64 (one wave); each pixel has NV = (C+2)*M values (in value_index order). A tile
+// holds two parts:
+//   rows   - the first npc 16-byte chunks of every lane: row c holds values [c*vpc, (c+1)*vpc)
+//            of lanes 0..63 as [lane][16 B] (vpc = 16 / sizeof(value)), so one wave instruction
+//            moves 1 KB of contiguous memory. npc covers the values a steady-state frame reads
+//            (the fast-path prefix) whenever NV leaves room for them in whole chunks;
+//   suffix - the remaining values of each lane, contiguous per lane and padded to whole 32-bit
+//            words: lane L's at npc KB + L*sb. A pixel that leaves the fast path reads and
+//            writes its suffix as a few contiguous bytes, not as 16-byte pieces of rows shared
+//            with 63 other pixels (whole sectors of which the memory would move).
+// A lane's tile + lane byte offset lives in one VGPR and every other offset is a compile-time
+// constant, so each state access is one buffer instruction. The range checked by the hardware
+// (num_records) is the whole block: an access outside it reads 0 and drops its write instead of
+// touching other memory. The host keeps every block below 4 GiB.
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
 constexpr uint32_t kChunkBytes = 16;
+constexpr uint32_t kRowBytes = 64u * kChunkBytes;
 
-// Byte offset, inside its tile, of value v of lane `lane` (nv values per pixel, es bytes each).
-__host__ __device__ constexpr uint32_t tile_value_offset(uint32_t v, uint32_t lane, uint32_t nv, uint32_t es) {
-  const uint32_t vpc = kChunkBytes / es;
-  const uint32_t nc = nv / vpc;
-  const uint32_t nf = nc * vpc;
-  return v < nf ? (v / vpc) * (64u * kChunkBytes) + lane * kChunkBytes + (v % vpc) * es
-                : nc * (64u * kChunkBytes) + (v - nf) * 64u * es + lane * es;
+struct TileLayout {
+  uint32_t vpc;    // values per 16-byte chunk
+  uint32_t npc;    // chunk rows
+  uint32_t rest;   // values per lane in the suffix
+  uint32_t sb;     // suffix bytes per lane (whole words)
+  uint32_t bytes;  // bytes per tile
+};
+
+__host__ __device__ constexpr TileLayout tile_layout(uint32_t M, uint32_t C, uint32_t es) {
+  const uint32_t nv = (C + 2) * M, vpc = kChunkBytes / es;
+  const uint32_t want = (fast_load_count(M, C) + vpc - 1) / vpc, whole = nv / vpc;
+  const uint32_t npc = want < whole ? want : whole;
+  const uint32_t rest = nv - npc * vpc;
+  const uint32_t sb = (rest * es + 3u) / 4u * 4u;
+  return TileLayout{vpc, npc, rest, sb, npc * kRowBytes + 64u * sb};
+}
+
+// Byte offset, inside its tile, of value v of lane `lane`.
+__host__ __device__ constexpr uint32_t tile_value_offset(uint32_t v, uint32_t lane, uint32_t M, uint32_t C,
+                                                         uint32_t es) {
+  const TileLayout L = tile_layout(M, C, es);
+  return v < L.npc * L.vpc ? (v / L.vpc) * kRowBytes + lane * kChunkBytes + (v % L.vpc) * es
+                           : L.npc * kRowBytes + lane * L.sb + (v - L.npc * L.vpc) * es;
 }
 
 struct StateBlock {
   __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t tile_bytes;  // P*M*64*sizeof(S)
+  uint32_t tile_bytes;
 };
 
-__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, int esize, int planes) {
-  const uint32_t tb = static_cast<uint32_t>(planes * kWave * esize);
-  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(tb * tiles64), kRsrcWord3), tb};
+__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, uint32_t tile_bytes) {
+  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(tile_bytes * tiles64), kRsrcWord3),
+                    tile_bytes};
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename S> struct BufIO;
 template <> struct BufIO<float> {
-  // the b32 builtins move raw 32-bit words: reinterpret, never convert
-  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, off, 0, 0));
-  }
-  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.rsrc, off, 0, 0);
-  }
-  static __device__ __forceinline__ float from_word(uint32_t w, int) { return __builtin_bit_cast(float, w); }
   // the 32-bit word holding value a (and b, for 16-bit types, in the high half); by value, so
   // the values stay in registers
   static __device__ __forceinline__ uint32_t word(float a, float) { return __builtin_bit_cast(uint32_t, a); }
+  // value `half` of a word (the lower-addressed one first); the b32/b128 builtins move raw
+  // words: reinterpret, never convert
+  static __device__ __forceinline__ float from_word(uint32_t w, int) { return __builtin_bit_cast(float, w); }
 };
 template <> struct BufIO<f16s> {
-  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
-    return Storage<f16s>::load(f16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, 0, 0)});
-  }
-  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(Storage<f16s>::pack(v).b, b.rsrc, off, 0, 0);
-  }
-  // a word holds two values, the lower-addressed one in the low half
   static __device__ __forceinline__ float from_word(uint32_t w, int half) {
     return Storage<f16s>::load(f16s{static_cast<uint16_t>(half ? (w >> 16) : (w & 0xFFFFu))});
   }
@@ -164,12 +185,6 @@ template <> struct BufIO<f16s> {
   }
 };
 template <> struct BufIO<bf16s> {
-  static __device__ __forceinline__ float ld(const StateBlock& b, uint32_t off) {
-    return Storage<bf16s>::load(bf16s{__builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, 0, 0)});
-  }
-  static __device__ __forceinline__ void st(const StateBlock& b, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(Storage<bf16s>::pack(v).b, b.rsrc, off, 0, 0);
-  }
   static __device__ __forceinline__ float from_word(uint32_t w, int half) {
     return __builtin_bit_cast(float, half ? (w & 0xFFFF0000u) : (w << 16));
   }
@@ -178,42 +193,34 @@ template <> struct BufIO<bf16s> {
   }
 };
 
-// Bytes of state one wave moves when it reads (or writes) values [0, LIMIT): whole chunks and
-// single rows that start below LIMIT, for all 64 lanes.
-template <int NV, int LIMIT, typename S>
-__host__ __device__ constexpr uint32_t prefix_bytes() {
-  constexpr uint32_t es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc;
-  uint32_t chunks = 0, singles = 0;
-  for (uint32_t c = 0; c < nc; ++c)
-    if (c * vpc < static_cast<uint32_t>(LIMIT)) ++chunks;
-  for (uint32_t j = nf; j < static_cast<uint32_t>(NV); ++j)
-    if (j < static_cast<uint32_t>(LIMIT)) ++singles;
-  return chunks * 64u * kChunkBytes + singles * 64u * es;
-}
-
-// Whether load_values<NV, LIMIT, S> reads value v: its whole 16-byte chunk comes along when the
-// chunk starts below LIMIT, so a chunk may carry values at or beyond LIMIT.
-template <int NV, int LIMIT, typename S>
+// Whether a load of values [0, LIMIT) reads value v: a chunk row comes whole when it starts
+// below LIMIT (so it may carry values at or beyond LIMIT), and the suffix comes whole when
+// LIMIT reaches into it.
+template <int M, int C, int LIMIT, typename S>
 __host__ __device__ constexpr bool value_read(uint32_t v) {
-  constexpr uint32_t vpc = kChunkBytes / sizeof(S), nf = (NV / vpc) * vpc;
-  return v < nf ? (v / vpc) * vpc < static_cast<uint32_t>(LIMIT) : v < static_cast<uint32_t>(LIMIT);
+  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
+  return v < L.npc * L.vpc ? (v / L.vpc) * L.vpc < static_cast<uint32_t>(LIMIT)
+                           : static_cast<uint32_t>(LIMIT) > L.npc * L.vpc;
 }
 
-// Every value a store of [0, SF) writes (whole chunks) is one a load of [0, LF) read.
-template <int NV, int LF, int SF, typename S>
+// Every value a store of [0, SF) writes is one a load of [0, LF) read.
+template <int M, int C, int LF, int SF, typename S>
 __host__ __device__ constexpr bool stores_only_read() {
-  for (uint32_t v = 0; v < static_cast<uint32_t>(NV); ++v)
-    if (value_read<NV, SF, S>(v) && !value_read<NV, LF, S>(v)) return false;
+  for (uint32_t v = 0; v < static_cast<uint32_t>((C + 2) * M); ++v)
+    if (value_read<M, C, SF, S>(v) && !value_read<M, C, LF, S>(v)) return false;
   return true;
 }
 
-// Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
-// it: all weights, rank 0 (variance, means) and the variance of rank 1.
-template <int M, int C>
-constexpr int kFastLoad = M > 1 ? M + (C + 1) + 1 : M + (C + 1);
-// ... and the values such a frame changes: all weights and rank 0.
-template <int M, int C>
-constexpr int kFastStore = M + (C + 1);
+// Bytes of state one wave moves when its 64 lanes read (or write) values [0, LIMIT), as
+// load_mix / store_mix move them.
+template <int M, int C, int LIMIT, typename S>
+__host__ __device__ constexpr uint32_t prefix_bytes() {
+  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
+  uint32_t rows = 0;
+  for (uint32_t c = 0; c < L.npc; ++c)
+    if (c * L.vpc < static_cast<uint32_t>(LIMIT)) ++rows;
+  return rows * kRowBytes + (static_cast<uint32_t>(LIMIT) > L.npc * L.vpc ? 64u * L.sb : 0u);
+}
 
 // Value V (in value_index order) of a pixel's mixture, as the Mix field that holds it.
 template <int M, int C, int V>
@@ -231,60 +238,99 @@ __device__ __forceinline__ float field(const Mix<M, C>& m) {
   return field<M, C, V>(const_cast<Mix<M, C>&>(m));
 }
 
-// Values [0, LIMIT) of pixel p, straight into the Mix: every 16-byte chunk and single value
-// that starts below LIMIT (whole chunks, so a little beyond LIMIT may come along; see
-// value_read). A value not read is left at 0 - a variance at 1, so that keys stay finite (any
-// use of it is discarded by the caller). LIMIT = NV reads everything.
+// Values [0, LIMIT) of pixel p, straight into the Mix (see value_read for what comes along). A
+// value not read is left at 0 - a variance at 1, so that keys stay finite (any use of it is
+// discarded by the caller). LIMIT = NV reads everything.
 template <int M, int C, typename S, int LIMIT = (C + 2) * M>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr int NV = (C + 2) * M, es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc,
-                vpw = 4 / es;
+  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr TileLayout L = tile_layout(M, C, es);
+  constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_bytes;
   static_for<0, NV>([&](auto v_) RGBD_BODY {
     constexpr int v = RGBD_I(v_);
-    if constexpr (!value_read<NV, LIMIT, S>(v)) field<M, C, v>(m) = (v >= M && (v - M) % (C + 1) == 0) ? 1.f : 0.f;
+    if constexpr (!value_read<M, C, LIMIT, S>(v)) field<M, C, v>(m) = (v >= M && (v - M) % (C + 1) == 0) ? 1.f : 0.f;
   });
-  static_for<0, nc>([&](auto c_) RGBD_BODY {
+  static_for<0, npc>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
     if constexpr (c * vpc < LIMIT) {
-      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
       static_for<0, vpc>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         field<M, C, c * vpc + i>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
       });
     }
   });
-  static_for<nf, NV>([&](auto j_) RGBD_BODY {
-    constexpr int j = RGBD_I(j_);
-    if constexpr (j < LIMIT) field<M, C, j>(m) = BufIO<S>::ld(b, base + tile_value_offset(j, lane, NV, es));
-  });
+  if constexpr (LIMIT > nf && nw > 0) {
+    const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
+    // whole 16-byte groups of the suffix, then single words
+    static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
+      constexpr int g = RGBD_I(g_);
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, sbase + 16u * g, 0, 0);
+      static_for<0, 4 * vpw>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        constexpr int v = nf + (4 * g) * vpw + i;
+        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
+      });
+    });
+    static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
+      constexpr int wi = RGBD_I(w_);
+      const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, sbase + 4u * wi, 0, 0);
+      static_for<0, vpw>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        constexpr int v = nf + wi * vpw + i;
+        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w, i);
+      });
+    });
+  }
 }
 
-// Values [0, LIMIT) of pixel p from the Mix (whole chunks, as load_mix reads them).
+// Values [0, LIMIT) of pixel p from the Mix (whole chunk rows and the whole suffix, as load_mix
+// reads them).
 template <int M, int C, typename S, int LIMIT = (C + 2) * M>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr int NV = (C + 2) * M, es = sizeof(S), vpc = kChunkBytes / es, nc = NV / vpc, nf = nc * vpc,
-                vpw = 4 / es;
+  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr TileLayout L = tile_layout(M, C, es);
+  constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_bytes;
-  static_for<0, nc>([&](auto c_) RGBD_BODY {
+  // suffix value v, or 0 for a padding half
+  auto sv = [&](auto v_) RGBD_BODY -> float {
+    constexpr int v = RGBD_I(v_);
+    if constexpr (v < NV) return field<M, C, v>(m);
+    else return 0.f;
+  };
+  static_for<0, npc>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
     if constexpr (c * vpc < LIMIT) {
-      // a zero (not undefined) start: element 0 is then never widened into a 16-byte load
-      // from the mixture, which would pin the mixture in memory
       u32x4 w = {0u, 0u, 0u, 0u};
       static_for<0, 4>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         w[i] = BufIO<S>::word(field<M, C, c * vpc + i * vpw>(m), field<M, C, c * vpc + i * vpw + vpw - 1>(m));
       });
-      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * 64u * kChunkBytes, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
     }
   });
-  static_for<nf, NV>([&](auto j_) RGBD_BODY {
-    constexpr int j = RGBD_I(j_);
-    if constexpr (j < LIMIT) BufIO<S>::st(b, base + tile_value_offset(j, lane, NV, es), field<M, C, j>(m));
-  });
+  if constexpr (LIMIT > nf && nw > 0) {
+    const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
+    static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
+      constexpr int g = RGBD_I(g_);
+      u32x4 w = {0u, 0u, 0u, 0u};
+      static_for<0, 4>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        constexpr int v = nf + (4 * g + i) * vpw;
+        w[i] = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+      });
+      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, sbase + 16u * g, 0, 0);
+    });
+    static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
+      constexpr int wi = RGBD_I(w_);
+      constexpr int v = nf + wi * vpw;
+      const uint32_t w = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+      __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, sbase + 4u * wi, 0, 0);
+    });
+  }
 }
 
 // The matched component's new mean, variance and weight (from the values before the update and

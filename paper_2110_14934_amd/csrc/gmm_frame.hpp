@@ -68,7 +68,7 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   constexpr int NV = (C + 2) * M;
   constexpr int LF = kFastLoad<M, C>;
   constexpr int SF = kFastStore<M, C>;
-  static_assert(stores_only_read<NV, LF, SF, S>(), "the fast path writes back a value it did not read");
+  static_assert(stores_only_read<M, C, LF, SF, S>(), "the fast path writes back a value it did not read");
   bool fg = false;
   const bool slow = active && !fast_step<M, C>(m, x, k);
   if (slow) {
@@ -80,8 +80,8 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
     store_mix<M, C, S, SF>(m, blk, p);
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
-  wave_bytes += (n_valid - n_slow) * ((prefix_bytes<NV, LF, S>() + prefix_bytes<NV, SF, S>()) / kWave) +
-                n_slow * (2u * prefix_bytes<NV, NV, S>() / kWave);
+  wave_bytes += (n_valid - n_slow) * ((prefix_bytes<M, C, LF, S>() + prefix_bytes<M, C, SF, S>()) / kWave) +
+                n_slow * (2u * prefix_bytes<M, C, NV, S>() / kWave);
   return fg;
 }
 
@@ -97,7 +97,7 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   bool fgc = false, fgd = false;
   uint32_t wave_bytes = 0;
   if (AUG && (mode & kModeAug) != 0) {
-    const StateBlock blk = make_block(a.st_rgb, a.tiles64, sizeof(S), 6 * M);
+    const StateBlock blk = make_block(a.st_rgb, a.tiles64, tile_layout(M, 4, sizeof(S)).bytes);
     Mix<M, 4> m;
     load_prefix<M, 4, S>(m, blk, p, valid);
     const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
@@ -110,8 +110,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
   const bool do_c = (mode & kModeRGB) != 0, do_d = (mode & kModeDepth) != 0, do_f = (mode & kModeFuse) != 0;
-  const StateBlock blk_c = make_block(a.st_rgb, a.tiles64, sizeof(S), 5 * M);
-  const StateBlock blk_d = make_block(a.st_depth, a.tiles64, sizeof(S), 3 * M);
+  const StateBlock blk_c = make_block(a.st_rgb, a.tiles64, tile_layout(M, 3, sizeof(S)).bytes);
+  const StateBlock blk_d = make_block(a.st_depth, a.tiles64, tile_layout(M, 1, sizeof(S)).bytes);
   Mix<M, 3> mc;
   Mix<M, 1> md;
   float xd = 0.f;

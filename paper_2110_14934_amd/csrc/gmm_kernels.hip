@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
 }
 
 // Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks), tiled layout.
+// (Padding halves of 16-bit suffix words are never read.)
 template <typename S>
 __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, int M, int C, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -55,7 +56,8 @@ __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, i
   const uint32_t lane = static_cast<uint32_t>(i % kWave);
   const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
   const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
-  const int64_t byte = tile * nv * kWave * static_cast<int64_t>(sizeof(S)) + tile_value_offset(v, lane, nv, sizeof(S));
+  const uint32_t tb = tile_layout(static_cast<uint32_t>(M), static_cast<uint32_t>(C), sizeof(S)).bytes;
+  const int64_t byte = tile * tb + tile_value_offset(v, lane, static_cast<uint32_t>(M), static_cast<uint32_t>(C), sizeof(S));
   // value order: M weights, then per rank (variance, C means)
   const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
   *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(is_var ? var0 : 0.f);
