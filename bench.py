@@ -228,6 +228,7 @@ def bench_batch(args) -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": f"rgbd::batch_kernel<{M}, {dtype}, {batch.tuning()[0]}>",
                      "algorithmic_bytes_per_launch": alg, "full_rewrite_bytes_per_launch": full,
+                     "full_rewrite_frac": full / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_us": ms_step * 1e3},
         "state_bytes": sum(sg.state_bytes() for sg in segs),
     }
@@ -500,6 +501,7 @@ def main(argv=None) -> int:
                      "kernel": f"rgbd::frame_kernel<5, float, {8 if augmented else 7}>",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "full_rewrite_bytes_per_launch": None if augmented else sorted_bytes,
+                     "full_rewrite_frac": None if augmented else sorted_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_us": ms_step * 1e3,
                      "device_copy_same_bytes_gbs": copy_gbs},
         "frames_per_s": 1e3 / ms_step,
