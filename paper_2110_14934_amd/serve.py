@@ -363,6 +363,10 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         if not add_stream(t0):
             break
     start = server.x.now()
+    # the initial streams' first arrivals count from the start of the run, not from before the
+    # joins (which allocate and initialise state for every stream)
+    heap = [(t + (start - t0), sid) for t, sid in heap]
+    heapq.heapify(heap)
     end = start + duration_s
     measure_from = start + warmup_s
     next_churn = start + (1.0 / churn_per_s if churn_per_s > 0 else math.inf)
