@@ -280,10 +280,11 @@ gmm_status gmm_batch_tiles(const gmm_batch* b, uint32_t* n_tiles);
 typedef struct gmm_exec gmm_exec;
 
 /* One stream's frame in a tick. Frames are read from host memory with dense rows (pitch
- * 3*width for colour, 2*width for depth); masks are written to host memory. Host buffers should
- * be pinned (page-locked) for the copies to overlap; they must stay valid and untouched until
- * the tick completes (gmm_exec_poll). A NULL mask pointer skips copying that mask back;
- * non-NULL host_fused runs List 1 for the stream (two-modality streams only). */
+ * 3*width for colour, 2*width for depth) by DMA; masks are written to host memory. Host buffers
+ * should be page-locked (hipHostMalloc, pinned torch tensors) for the copies to overlap device
+ * work; they must stay valid and untouched until the tick completes (gmm_exec_poll). A NULL
+ * mask pointer skips copying that mask back; non-NULL host_fused runs List 1 for the stream
+ * (two-modality streams only). */
 typedef struct {
   gmm_handle* handle;
   const uint8_t* host_rgb;
@@ -304,17 +305,18 @@ gmm_status gmm_exec_create(int32_t device, int32_t ring, gmm_exec** out);
 gmm_status gmm_exec_destroy(gmm_exec* x);
 /* Launch shape of the batched kernel (same meaning and limits as gmm_batch_tuning). */
 gmm_status gmm_exec_set_tuning(gmm_exec* x, const gmm_batch_tuning* t);
-/* Give a stream a device frame slot and device masks (all streams of an executor share M and
- * the state dtype). Reports the device bytes this adds, for memory admission.
+/* Give a stream two device frame slots, used by its frames in turn so that one frame can be
+ * copied in while the previous one computes (all streams of an executor share M and the state
+ * dtype). Reports the device bytes this adds, for memory admission.
  * GMM_ERR_UNSUPPORTED for a GMM_AUGMENTED handle (also in the two calls below). */
 gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes);
-/* Release a stream's slot after its last tick has completed (waits for it). */
+/* Release a stream's frame slots after its last tick has completed (waits for it). */
 gmm_status gmm_exec_detach(gmm_exec* x, gmm_handle* h);
 /* Device bytes of a stream created by gmm_exec_create_stream: its state (as gmm_state_bytes)
- * rounded up to 256 bytes, then its frame slot. */
+ * rounded up to 256 bytes, then its two frame slots. */
 gmm_status gmm_exec_stream_bytes(const gmm_config* cfg, size_t* bytes);
 /*
- * Create and attach a stream whose state and frame slot live in caller-provided device memory
+ * Create and attach a stream whose state and frame slots live in caller-provided device memory
  * `mem` (256-byte aligned, at least gmm_exec_stream_bytes). The state is initialised on the
  * executor's compute stream, ordered before every later tick: no allocation and no host
  * synchronisation, so streams can join a running server without stalling it. The caller keeps
@@ -326,10 +328,11 @@ gmm_status gmm_exec_create_stream(gmm_exec* x, const gmm_config* cfg, void* mem,
  * (waits for that tick only); frees no device memory. */
 gmm_status gmm_exec_destroy_stream(gmm_exec* x, gmm_handle* h);
 /*
- * Advance the given streams (each at most once, none with a frame still in flight) by one frame
- * in one tick; returns at once with the tick's id (ids increase by 1 from 1). Blocks only when
- * `ring` ticks are already in flight. Per stream, masks and state are bit-identical to
- * gmm_apply_frame / gmm_apply_frame_fused on the same frame.
+ * Advance the given streams (each at most once, none with two frames still in flight) by one
+ * frame in one tick; returns at once with the tick's id (ids increase by 1 from 1). A stream's
+ * frames are applied in launch order. Blocks only when `ring` ticks are already in flight. Per
+ * stream, masks and state are bit-identical to gmm_apply_frame / gmm_apply_frame_fused on the
+ * same frames.
  */
 gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, uint64_t* tick_id);
 /* Completed ticks since the last poll, in launch order: ids and completion times (at most cap). */

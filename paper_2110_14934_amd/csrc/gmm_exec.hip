@@ -55,13 +55,35 @@ using namespace rgbd;
 
 namespace {
 
+// A stream's two device frame slots: its frames alternate between them, so frame n+1 can be
+// copied in while the tick holding frame n still computes (the state itself is ordered by the
+// compute stream). At most two frames of a stream are in flight.
+constexpr int kFramesInFlight = 2;
+
 struct Attached {
-  void* base = nullptr;           // the one device allocation holding the slots below
-  uint8_t* d_rgb = nullptr;       // dense input slot (3 bytes per pixel)
-  uint16_t* d_depth = nullptr;    // dense input slot (2 bytes per pixel)
+  void* base = nullptr;                        // the device allocation holding the slots (or none)
+  uint8_t* d_rgb[kFramesInFlight] = {};        // dense colour slots (3 bytes per pixel)
+  uint16_t* d_depth[kFramesInFlight] = {};     // dense depth slots (2 bytes per pixel)
   size_t bytes = 0;
   int in_flight = 0;
+  uint64_t frames = 0;                         // frames launched; frame f uses slot f % 2
 };
+
+// Bytes of one frame slot of h: colour then depth, each rounded up to 256 bytes.
+static size_t frame_slot_bytes(const gmm_handle* h) {
+  const size_t n = static_cast<size_t>(h->npix);
+  return (has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0) + (has_depth(h) ? (n * 2 + 255) / 256 * 256 : 0);
+}
+
+// Lays the two frame slots of h out from p (256-byte aligned).
+static void place_slots(Attached& a, const gmm_handle* h, uint8_t* p) {
+  const size_t n = static_cast<size_t>(h->npix), rgb = has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0;
+  for (int k = 0; k < kFramesInFlight; ++k) {
+    uint8_t* q = p + static_cast<size_t>(k) * frame_slot_bytes(h);
+    a.d_rgb[k] = has_rgb(h) ? q : nullptr;
+    a.d_depth[k] = has_depth(h) ? reinterpret_cast<uint16_t*>(q + rgb) : nullptr;
+  }
+}
 
 constexpr int kCopyInStreams = 4;  // host->device copies spread over several DMA queues
 
@@ -237,18 +259,15 @@ gmm_status gmm_exec_attach(gmm_exec* x, gmm_handle* h, size_t* device_bytes) {
   if (x->attached.count(h)) return fail(GMM_ERR_INVALID_ARG, "handle already attached");
   if (x->M >= 0 && (h->cfg.M != x->M || h->cfg.state_dtype != x->dtype))
     return fail(GMM_ERR_INVALID_ARG, "all streams of an executor need the same M and state dtype");
-  const size_t rgb = has_rgb(h) ? (static_cast<size_t>(h->npix) * 3 + 255) / 256 * 256 : 0;
-  const size_t dep = has_depth(h) ? (static_cast<size_t>(h->npix) * 2 + 255) / 256 * 256 : 0;
+  const size_t slots = kFramesInFlight * frame_slot_bytes(h);
   DeviceGuard g(x->device);
   void* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, rgb + dep);
-  if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "device allocation of the stream's frame slot failed");
+  hipError_t e = hipMalloc(&mem, slots);
+  if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "device allocation of the stream's frame slots failed");
   Attached a;
-  uint8_t* base = static_cast<uint8_t*>(mem);
   a.base = mem;
-  a.d_rgb = rgb ? base : nullptr;
-  a.d_depth = dep ? reinterpret_cast<uint16_t*>(base + rgb) : nullptr;
-  a.bytes = rgb + dep;
+  place_slots(a, h, static_cast<uint8_t*>(mem));
+  a.bytes = slots;
   x->attached[h] = a;
   x->M = h->cfg.M;
   x->dtype = h->cfg.state_dtype;
@@ -281,7 +300,8 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
       const gmm_exec_item& it = items[i];
       auto f = it.handle ? x->attached.find(it.handle) : x->attached.end();
       if (f == x->attached.end()) return fail(GMM_ERR_INVALID_ARG, "item " + std::to_string(i) + ": handle not attached");
-      if (f->second.in_flight) return fail(GMM_ERR_STATE, "item " + std::to_string(i) + ": stream has a frame in flight");
+      if (f->second.in_flight >= kFramesInFlight)
+        return fail(GMM_ERR_STATE, "item " + std::to_string(i) + ": stream already has two frames in flight");
       for (int32_t j = 0; j < i; ++j)
         if (items[j].handle == it.handle) return fail(GMM_ERR_INVALID_ARG, "a stream appears twice in one tick");
       const gmm_handle* h = it.handle;
@@ -358,7 +378,8 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     const gmm_exec_item& it = items[i];
     gmm_handle* h = it.handle;
     auto dm = [&](int k) { return moff[3 * i + k] == SIZE_MAX ? nullptr : s.d_masks + moff[3 * i + k] / 8; };
-    s.h_table[i] = frame_args(h, att[i].d_rgb, 3 * static_cast<int64_t>(h->cfg.width), att[i].d_depth,
+    const int k = static_cast<int>(att[i].frames % kFramesInFlight);
+    s.h_table[i] = frame_args(h, att[i].d_rgb[k], 3 * static_cast<int64_t>(h->cfg.width), att[i].d_depth[k],
                               2 * static_cast<int64_t>(h->cfg.width), dm(0), dm(1), dm(2));
     const size_t mb = mask_bytes(h);
     if (it.host_fg_rgb) s.outs.push_back({it.host_fg_rgb, moff[3 * i], mb});
@@ -377,23 +398,26 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     if (e != hipSuccess) return fail(GMM_ERR_OUT_OF_MEMORY, "device tile-map allocation failed");
     s.map_cap = total_tiles * 2;
   }
-  // copy-in: frames from host memory into the streams' device slots, each frame on the least
-  // loaded of the copy-in streams (by bytes), so several DMA engines work at once
+  // copy-in: frames from host memory into the streams' device frame slots, each frame on the
+  // least loaded of the copy-in streams (by bytes), so several DMA engines work at once. DMA
+  // engines need no compute units, so the copies of one tick overlap the previous tick's kernel.
+  // The slot a frame goes to was last read by the stream's frame before last, whose tick has
+  // completed: a stream is accepted here only with at most one frame in flight.
   size_t queued[kCopyInStreams] = {};
   for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
     const gmm_handle* h = items[i].handle;
+    const size_t px = static_cast<size_t>(h->npix);
+    const int k = static_cast<int>(att[i].frames % kFramesInFlight);
     int q = 0;
     for (int c = 1; c < kCopyInStreams; ++c)
       if (queued[c] < queued[q]) q = c;
     if (items[i].host_rgb) {
-      e = hipMemcpyAsync(att[i].d_rgb, items[i].host_rgb, static_cast<size_t>(h->npix) * 3, hipMemcpyHostToDevice,
-                         x->s_in[q]);
-      queued[q] += static_cast<size_t>(h->npix) * 3;
+      e = hipMemcpyAsync(att[i].d_rgb[k], items[i].host_rgb, px * 3, hipMemcpyHostToDevice, x->s_in[q]);
+      queued[q] += px * 3;
     }
     if (e == hipSuccess && items[i].host_depth) {
-      e = hipMemcpyAsync(att[i].d_depth, items[i].host_depth, static_cast<size_t>(h->npix) * 2, hipMemcpyHostToDevice,
-                         x->s_in[q]);
-      queued[q] += static_cast<size_t>(h->npix) * 2;
+      e = hipMemcpyAsync(att[i].d_depth[k], items[i].host_depth, px * 2, hipMemcpyHostToDevice, x->s_in[q]);
+      queued[q] += px * 2;
     }
   }
   for (int c = 0; c < kCopyInStreams && e == hipSuccess; ++c) e = hipEventRecord(s.h2d_done[c], x->s_in[c]);
@@ -427,7 +451,9 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     s.handles.clear();
     for (int32_t i = 0; i < n; ++i) {
       s.handles.push_back(items[i].handle);
-      x->attached[items[i].handle].in_flight++;
+      Attached& a = x->attached[items[i].handle];
+      a.in_flight++;
+      a.frames++;
       items[i].handle->last_stream = x->s_compute;
     }
     x->pending.push_back(si);
@@ -447,9 +473,7 @@ gmm_status gmm_exec_stream_bytes(const gmm_config* cfg, size_t* bytes) {
     delete h;
     return fail(GMM_ERR_UNSUPPORTED, "augmented handles run one at a time");
   }
-  const size_t n = static_cast<size_t>(h->npix);
-  const size_t slot = (has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0) + (has_depth(h) ? (n * 2 + 255) / 256 * 256 : 0);
-  *bytes = (state_bytes(h) + 255) / 256 * 256 + slot;
+  *bytes = (state_bytes(h) + 255) / 256 * 256 + kFramesInFlight * frame_slot_bytes(h);
   delete h;
   return GMM_OK;
 }
@@ -473,11 +497,9 @@ gmm_status gmm_exec_create_stream(gmm_exec* x, const gmm_config* cfg, void* mem,
   uint8_t* base = static_cast<uint8_t*>(mem);
   place_state(h, base);
   const size_t sb = (state_bytes(h) + 255) / 256 * 256;
-  const size_t n = static_cast<size_t>(h->npix);
   Attached a;
   a.base = nullptr;  // the caller's memory: never freed here
-  a.d_rgb = has_rgb(h) ? base + sb : nullptr;
-  a.d_depth = has_depth(h) ? reinterpret_cast<uint16_t*>(base + sb + (has_rgb(h) ? (n * 3 + 255) / 256 * 256 : 0)) : nullptr;
+  place_slots(a, h, base + sb);
   a.bytes = need;
   DeviceGuard g(x->device);
   // initialised on the compute stream: ordered before any tick that uses the stream

@@ -7,13 +7,15 @@ Policy (``Server``):
     memory budget next to the streams already admitted; otherwise the join is refused and the
     caller may retry later, when leaves have freed memory;
   * each stream keeps a FIFO of submitted frames (bounded; a frame arriving to a full queue is
-    dropped and counted). At most one frame per stream is on the device at a time, since every
-    frame reads and rewrites that stream's state;
+    dropped and counted). At most ``executor.frames_in_flight`` frames per stream are on the
+    device at a time (the native executor: two, one per device frame slot; every frame reads
+    and rewrites the stream's state, and the executor applies a stream's frames in launch
+    order, so frame n+1 can be copied in while frame n computes);
   * continuous batching: every ``step`` first collects completed ticks, then launches ONE tick
-    holding the oldest queued frame of every stream that has no frame in flight. Frames that
-    arrive while earlier ticks run join the next tick; up to the executor's ring of ticks are on
-    the device at once, overlapping their copies and kernels;
-  * leave: queued frames of the stream are cancelled, its in-flight frame completes, then its
+    holding the oldest queued frame of every stream below that limit. Frames that arrive while
+    earlier ticks run join the next tick; up to the executor's ring of ticks are on the device
+    at once, overlapping their copies and kernels;
+  * leave: queued frames of the stream are cancelled, its in-flight frames complete, then its
     memory is released.
 
 The scheduling logic only talks to an executor object (``open_stream``, ``close_stream``,
@@ -61,7 +63,7 @@ class ServedStream:
     handle: object
     bytes: int
     queue: deque = field(default_factory=deque)
-    in_flight: Optional[FrameRequest] = None
+    in_flight: int = 0           # frames of the stream on the device
     leaving: bool = False
 
     @property
@@ -76,6 +78,7 @@ class ServedStream:
 class Server:
     def __init__(self, executor, hbm_budget_bytes: int, max_queue: int = 8):
         self.x = executor
+        self.depth = int(getattr(executor, "frames_in_flight", 1))
         self.budget = int(hbm_budget_bytes)
         self.max_queue = max_queue
         self.streams: Dict[int, ServedStream] = {}
@@ -107,7 +110,7 @@ class Server:
         self.stats["cancelled"] += len(st.queue)
         st.queue.clear()
         self.stats["left"] += 1
-        if st.in_flight is None:
+        if st.in_flight == 0:
             self._release(st)
 
     def _release(self, st: ServedStream):
@@ -128,7 +131,7 @@ class Server:
         return True
 
     def ready(self) -> List[ServedStream]:
-        return [s for s in self.streams.values() if s.in_flight is None and s.queue and not s.leaving]
+        return [s for s in self.streams.values() if s.in_flight < self.depth and s.queue and not s.leaving]
 
     def collect(self) -> List[FrameRequest]:
         """Frames of completed ticks (each with t_done and tick set)."""
@@ -139,8 +142,8 @@ class Server:
                 done.append(req)
                 st = self.streams.get(req.stream_id)
                 if st is not None:
-                    st.in_flight = None
-                    if st.leaving:
+                    st.in_flight -= 1
+                    if st.leaving and st.in_flight == 0:
                         self._release(st)
         self.stats["completed"] += len(done)
         return done
@@ -152,14 +155,14 @@ class Server:
         reqs = []
         for st in batch:
             req = st.queue.popleft()
-            st.in_flight = req
+            st.in_flight += 1
             reqs.append((st, req))
         try:
             tick = self.x.launch(reqs)
         except Exception:
             # nothing was enqueued: the frames go back to the head of their queues
             for st, req in reqs:
-                st.in_flight = None
+                st.in_flight -= 1
                 st.queue.appendleft(req)
             raise
         for _, req in reqs:
@@ -182,7 +185,7 @@ class Server:
         self.collect()
         for st in list(self.streams.values()):
             st.queue.clear()
-            if st.in_flight is None:
+            if st.in_flight == 0:
                 self._release(st)
 
 
@@ -229,6 +232,8 @@ class Arena:
 class NativeExecutor:
     """The GPU executor (gmm_exec_*). Stream state and frame slots are carved from one device
     reservation of `arena_bytes`, so joins and leaves allocate, free and synchronise nothing."""
+
+    frames_in_flight = 2  # a stream's two device frame slots
 
     def __init__(self, device: int = 0, ring: int = 4, M: int = 5, state_dtype: str = "f16",
                  tuning: Optional[Tuple[int, int, int]] = None, arena_bytes: int = 1 << 30, **params):
@@ -372,6 +377,10 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
     next_churn = start + (1.0 / churn_per_s if churn_per_s > 0 else math.inf)
     pending_joins = 0
     lat: List[float] = []
+    lat_t: List[float] = []       # arrival time of each measured frame, from the start
+    drops_at: List[int] = []      # server drop count at each whole second of the run
+    gap_max: List[float] = []     # longest pass of the loop below in each second of the run
+    prev = start
     pu_done = 0
     frames_done = 0
     last_report = start
@@ -379,6 +388,11 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         now = server.x.now()
         if now >= end:
             break
+        while len(drops_at) <= int(now - start):
+            drops_at.append(server.stats["dropped"])
+            gap_max.append(0.0)
+        gap_max[int(now - start)] = max(gap_max[int(now - start)], now - prev)
+        prev = now
         # churn: one stream leaves and one joins per period (joins retried until admitted)
         if now >= next_churn:
             live = [s for s in server.streams if not server.streams[s].leaving]
@@ -404,6 +418,7 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         for req in server.step():
             if req.t_arrival >= measure_from:
                 lat.append(req.t_done - req.t_arrival)
+                lat_t.append(req.t_arrival - start)
                 k = kinds[req.stream_id]
                 pu_done += k.width * k.height * ((k.modalities & GMM_RGB != 0) + (k.modalities & GMM_DEPTH != 0))
                 frames_done += 1
@@ -414,6 +429,18 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
     window = end - measure_from
     server.x.drain()
     server.collect()
+    drops_at.append(server.stats["dropped"])
+    # one entry per second of the measured window (by arrival time): frames completed, their p99
+    # latency, frames dropped in that second, and the longest pass of the serving loop (a long
+    # pass means the host thread itself was held up)
+    timeline = []
+    lat_a, lat_ta = np.asarray(lat), np.asarray(lat_t)
+    for sec in range(int(math.floor(warmup_s)), int(math.ceil(duration_s))):
+        sel = lat_a[(lat_ta >= sec) & (lat_ta < sec + 1)]
+        dropped = drops_at[min(sec + 1, len(drops_at) - 1)] - drops_at[min(sec, len(drops_at) - 1)]
+        timeline.append({"t": sec, "frames": int(sel.size), "dropped": int(dropped),
+                         "p99_ms": round(float(np.percentile(sel, 99)) * 1e3, 3) if sel.size else None,
+                         "loop_max_ms": round(gap_max[sec] * 1e3, 3) if sec < len(gap_max) else None})
     return {
         "streams_target": n_streams,
         "streams_end": len(server.streams),
@@ -425,6 +452,7 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         "p99_latency_ms": percentile(lat, 99) * 1e3,
         "max_latency_ms": (max(lat) * 1e3) if lat else math.nan,
         "stats": dict(server.stats),
+        "timeline": timeline,
         "hbm_used_bytes": server.used,
         "hbm_budget_bytes": server.budget,
     }

@@ -32,12 +32,35 @@ def words(sp):
     return (sp.npix + 63) // 64
 
 
-def test_executor_ticks_bit_identical_to_plain_path():
-    streams = [Stream(s) for s in SPECS]
+# a frame of several 64 KiB ingest pieces with a ragged last piece
+WIDE = StreamSpec(330, 241, n_boxes=2, box_min=20, box_max=40, hole_p=0.02, seed=71, index=4)
+
+
+def host_frame(t, how, k):
+    """Frame t in host memory: pinned (read by the ingest kernel), pageable (copied by DMA), or
+    pinned at an odd offset inside a larger pinned allocation (ingest, unaligned pieces)."""
+    t = t.contiguous()
+    if how == "pageable":
+        return t.clone()
+    if how == "offset":
+        flat = t.reshape(-1)
+        e = flat.element_size()
+        buf = torch.empty(flat.numel() + 16 // e, dtype=flat.dtype).pin_memory()
+        view = buf[1 + k % 3:1 + k % 3 + flat.numel()]
+        view.copy_(flat)
+        return view
+    return t.pin_memory()
+
+
+@pytest.mark.parametrize("host_mem", ["pinned", "pageable", "mixed"])
+def test_executor_ticks_bit_identical_to_plain_path(host_mem):
+    specs = SPECS + [WIDE]
+    streams = [Stream(s) for s in specs]
     x = _abi.gmm_exec_create(0, 3)
     handles, refs, outs = [], [], []
+    how = {"pinned": ["pinned"], "pageable": ["pageable"], "mixed": ["pinned", "pageable", "offset"]}[host_mem]
     try:
-        for sp in SPECS:
+        for sp in specs:
             cfg = _abi.gmm_config_default(sp.width, sp.height, mods(sp), 5, state_dtype=_abi.GMM_F16)
             h = _abi.gmm_create(cfg)
             handles.append(h)
@@ -45,9 +68,10 @@ def test_executor_ticks_bit_identical_to_plain_path():
             refs.append(Segmenter(sp.width, sp.height, mods(sp), 5, state_dtype="f16"))
         for t in range(12):
             items, keep = [], []
-            for sp, st, h in zip(SPECS, streams, handles):
-                rgb = pinned(st.rgb(t)) if sp.rgb else None
-                dep = pinned(st.depth(t)) if sp.depth else None
+            for k, (sp, st, h) in enumerate(zip(specs, streams, handles)):
+                hw = how[(k + t) % len(how)]
+                rgb = host_frame(st.rgb(t), hw, k) if sp.rgb else None
+                dep = host_frame(st.depth(t), hw, k + 1) if sp.depth else None
                 o = [torch.zeros(words(sp), dtype=torch.int64).pin_memory() if on else None
                      for on in (sp.rgb, sp.depth, sp.rgb and sp.depth)]
                 it = _abi.gmm_exec_item()
@@ -61,7 +85,7 @@ def test_executor_ticks_bit_identical_to_plain_path():
                 keep.append((rgb, dep, o))
             tick = _abi.gmm_exec_launch(x, items)
             assert tick == t + 1
-            for sp, st, ref in zip(SPECS, streams, refs):
+            for sp, st, ref in zip(specs, streams, refs):
                 rgb = st.rgb(t, device=DEV) if sp.rgb else None
                 dep = st.depth(t, device=DEV) if sp.depth else None
                 if sp.rgb and sp.depth:
@@ -79,6 +103,80 @@ def test_executor_ticks_bit_identical_to_plain_path():
         for h, ref in zip(handles, refs):
             assert np.array_equal(_abi.gmm_read_state(h), ref.read_state())
     finally:
+        for h in handles:
+            _abi.gmm_exec_detach(x, h)
+            _abi.gmm_destroy(h)
+        _abi.gmm_exec_destroy(x)
+        for r in refs:
+            r.close()
+
+
+def _item(h, rgb, dep, o):
+    it = _abi.gmm_exec_item()
+    it.handle = h
+    it.host_rgb = rgb.data_ptr() if rgb is not None else None
+    it.host_depth = dep.data_ptr() if dep is not None else None
+    for name, b in zip(("host_fg_rgb", "host_fg_depth", "host_fused"), o):
+        setattr(it, name, b.data_ptr() if b is not None else None)
+    return it
+
+
+@pytest.mark.parametrize("ring", [2, 4])
+def test_two_frames_per_stream_in_flight(ring):
+    """Tick t+1 is launched before tick t completes, so every stream has two frames on the
+    device (one per frame slot) and the copy-in of one overlaps the compute of the other; masks
+    of every tick and the final state equal the plain path's."""
+    specs = SPECS + [WIDE]
+    streams = [Stream(s) for s in specs]
+    x = _abi.gmm_exec_create(0, ring)
+    handles, refs = [], []
+    T = 14
+    how = ["pinned", "pageable", "offset"]
+    try:
+        for sp in specs:
+            cfg = _abi.gmm_config_default(sp.width, sp.height, mods(sp), 5, state_dtype=_abi.GMM_F16)
+            h = _abi.gmm_create(cfg)
+            handles.append(h)
+            _abi.gmm_exec_attach(x, h)
+            refs.append(Segmenter(sp.width, sp.height, mods(sp), 5, state_dtype="f16"))
+        keep, want, done = {}, {}, []
+        for t in range(T):
+            items, kt = [], []
+            for k, (sp, st, h) in enumerate(zip(specs, streams, handles)):
+                hw = how[(k + t) % len(how)]
+                rgb = host_frame(st.rgb(t), hw, k) if sp.rgb else None
+                dep = host_frame(st.depth(t), hw, k + 1) if sp.depth else None
+                o = [torch.zeros(words(sp), dtype=torch.int64).pin_memory() if on else None
+                     for on in (sp.rgb, sp.depth, sp.rgb and sp.depth)]
+                items.append(_item(h, rgb, dep, o))
+                kt.append((rgb, dep, o))
+            tick = _abi.gmm_exec_launch(x, items)
+            keep[tick] = kt
+            w = []
+            for sp, st, ref in zip(specs, streams, refs):
+                rgb = st.rgb(t, device=DEV) if sp.rgb else None
+                dep = st.depth(t, device=DEV) if sp.depth else None
+                if sp.rgb and sp.depth:
+                    ref.apply_fused(rgb, dep)
+                else:
+                    ref.apply(rgb, dep)
+                w.append([m.cpu() if m is not None else None for m in (ref.fg_rgb, ref.fg_depth, ref.fused)])
+            want[tick] = w
+            # before the next launch, the tick before this one has to be complete
+            while not any(d[0] == tick - 1 for d in done) and tick > 1:
+                done += _abi.gmm_exec_poll(x)
+        _abi.gmm_exec_drain(x)
+        done += _abi.gmm_exec_poll(x)
+        assert [d[0] for d in done] == list(range(1, T + 1))
+        for tick in range(1, T + 1):
+            for (rgb, dep, o), w in zip(keep[tick], want[tick]):
+                for got, ref in zip(o, w):
+                    if got is not None:
+                        assert torch.equal(got, ref), tick
+        for h, ref in zip(handles, refs):
+            assert np.array_equal(_abi.gmm_read_state(h), ref.read_state())
+    finally:
+        _abi.gmm_exec_drain(x)
         for h in handles:
             _abi.gmm_exec_detach(x, h)
             _abi.gmm_destroy(h)

@@ -1,5 +1,5 @@
-"""The serving scheduler on the CPU, against a fake executor: admission by memory budget, one
-frame per stream in flight, FIFO order, continuous batching, leave while in flight, dropped
+"""The serving scheduler on the CPU, against a fake executor: admission by memory budget, at
+most the executor's number of frames per stream in flight (one or two), FIFO order, continuous batching, leave while in flight, dropped
 frames, and each stream's results identical alone and in a mix (the fake computes masks with
 the FP64 oracle, so a mixed-up frame or state would show)."""
 import math
@@ -14,13 +14,14 @@ from paper_2110_14934_amd.serve import Arena, FrameRequest, Server, run_load, St
 class FakeExecutor:
     """Completes ticks when told to (or after `latency` of its own clock); checks invariants."""
 
-    def __init__(self, latency=0.0, dt=0.0):
+    def __init__(self, latency=0.0, dt=0.0, depth=1):
+        self.frames_in_flight = depth
         self.t = 0.0
         self.dt = dt
         self.latency = latency
         self.next_tick = 1
         self.inflight = {}          # tick -> (t_launch, [stream ids])
-        self.busy = set()           # streams with a frame on the "device"
+        self.busy = {}              # stream -> frames on the "device"
         self.opened = {}
         self.last_seq = {}
         self.models = {}            # stream -> oracle (depth only, 1 channel)
@@ -49,11 +50,11 @@ class FakeExecutor:
         ids = []
         for st, r in reqs:
             assert st.handle in self.opened
-            assert st.handle not in self.busy, "two frames of one stream in flight"
+            assert self.busy.get(st.handle, 0) < self.frames_in_flight, "too many frames of one stream in flight"
             assert st.handle not in ids, "stream twice in a tick"
             assert self.last_seq.get(st.handle, -1) < r.seq, "frames out of order"
             self.last_seq[st.handle] = r.seq
-            self.busy.add(st.handle)
+            self.busy[st.handle] = self.busy.get(st.handle, 0) + 1
             ids.append(st.handle)
             fg = self.models[st.handle].step(np.asarray(r.depth, np.float64).reshape(-1, 1)).fg
             self.results[(st.id, r.seq)] = fg
@@ -67,9 +68,14 @@ class FakeExecutor:
         for tick in list(self.inflight):
             self._done.append((tick, self.t))
             for h in self.inflight.pop(tick)[1]:
-                self.busy.discard(h)
+                self._free(h)
 
     _done = None
+
+    def _free(self, h):
+        self.busy[h] -= 1
+        if self.busy[h] == 0:
+            del self.busy[h]
 
     def poll(self):
         if self._done is None:
@@ -80,7 +86,7 @@ class FakeExecutor:
                     self._done.append((tick, self.t))
                     del self.inflight[tick]
                     for h in ids:
-                        self.busy.discard(h)
+                        self._free(h)
         out, self._done = self._done, []
         return out
 
@@ -131,6 +137,41 @@ def test_one_frame_in_flight_fifo_and_continuous_batching():
     assert srv.in_flight() == 0
 
 
+def test_two_frames_in_flight_when_the_executor_has_two_slots():
+    x = FakeExecutor(depth=2)
+    x._done = []
+    srv = Server(x, 10 ** 6)
+    a, b = srv.join(2, 2, GMM_DEPTH), srv.join(2, 2, GMM_DEPTH)
+    for s in range(4):
+        assert srv.submit(_req(a, s))
+    srv.step()
+    srv.step()
+    srv.step()
+    assert x.launches == [1, 1]                          # a's seq 0 and 1; seq 2 waits for a slot
+    assert srv.streams[a].in_flight == 2 and [r.seq for r in srv.streams[a].queue] == [2, 3]
+    assert srv.submit(_req(b, 0))
+    srv.step()
+    assert x.launches == [1, 1, 1]                       # b is not held back by a
+    x.complete_all()
+    done = srv.step()
+    assert [(r.stream_id, r.seq) for r in done] == [(a, 0), (a, 1), (b, 0)]
+    assert x.launches == [1, 1, 1, 1]                    # a's seq 2 (seq 3 joins the next tick)
+    srv.step()
+    x.complete_all()
+    done = srv.step()
+    assert [(r.stream_id, r.seq) for r in done] == [(a, 2), (a, 3)]
+    assert srv.in_flight() == 0 and x.busy == {}
+    srv.submit(_req(a, 4))
+    srv.submit(_req(a, 5))
+    srv.step()
+    srv.step()
+    srv.leave(a)                                         # two in flight: memory held until both end
+    assert a in srv.streams
+    x.complete_all()
+    srv.step()
+    assert a not in srv.streams
+
+
 def test_leave_while_in_flight_releases_after_completion():
     x = FakeExecutor()
     x._done = []
@@ -159,12 +200,13 @@ def test_full_queue_drops_and_counts():
     assert srv.stats["dropped"] == 1 and srv.stats["submitted"] == 3
 
 
-def test_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("depth", [1, 2])
+def test_results_alone_equal_results_in_the_mix(depth):
     rng = np.random.default_rng(4)
     frames = [rng.integers(90, 110, 16).astype(np.uint16) for _ in range(30)]
 
     def run(mixed: bool):
-        x = FakeExecutor()
+        x = FakeExecutor(depth=depth)
         x._done = []
         srv = Server(x, 10 ** 6, max_queue=64)
         others = []
@@ -193,8 +235,9 @@ def test_results_alone_equal_results_in_the_mix():
         assert np.array_equal(p, q), t
 
 
-def test_run_load_accounting_with_fake_clock():
-    x = FakeExecutor(latency=0.010, dt=0.0005)
+@pytest.mark.parametrize("depth", [1, 2])
+def test_run_load_accounting_with_fake_clock(depth):
+    x = FakeExecutor(latency=0.010, dt=0.0005, depth=depth)
     srv = Server(x, 10 ** 9)
 
     class Px:   # a stand-in for a pinned frame; the fake only reads it as depth values
@@ -213,6 +256,9 @@ def test_run_load_accounting_with_fake_clock():
     assert rep["p99_latency_ms"] < 40.0
     assert rep["stats"]["left"] >= 3 and rep["stats"]["joined"] >= 8 + 3
     assert math.isfinite(rep["pixel_updates_per_s"])
+    assert [e["t"] for e in rep["timeline"]] == [0, 1]
+    assert sum(e["frames"] for e in rep["timeline"]) == rep["frames_completed"]
+    assert sum(e["dropped"] for e in rep["timeline"]) <= rep["stats"]["dropped"]
 
 
 def test_arena_first_fit_and_coalescing():
