@@ -54,8 +54,23 @@ def bytes_per_frame(npix: int, holes: float, M: int, esize: int) -> float:
     return colour + depth + fusion
 
 
-def alg_bytes_hint(npix: int, M: int, esize: int) -> float:
-    return bytes_per_frame(npix, 0.0, M, esize)
+def device_copy_gbs(nbytes: float, stream, reps: int) -> float:
+    """The practical read+write ceiling next to a launch: GB/s of a plain device copy that reads
+    nbytes/2 and writes nbytes/2 (the algorithmic bytes of one launch), timed on `stream`."""
+    import torch
+    half = int(nbytes // 2) // 4 * 4
+    src = torch.empty(half // 4, dtype=torch.float32, device=stream.device).fill_(1.0)
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            dst.copy_(src)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        c1.record(stream)
+    torch.cuda.synchronize()
+    return 2 * half / (c0.elapsed_time(c1) / reps / 1e3) / 1e9
 
 
 def io_bytes_per_frame(npix: int, rgb: bool = True, depth: bool = True, fused: bool = True) -> float:
@@ -216,6 +231,7 @@ def bench_batch(args) -> int:
     state = float(sum(int(r.sum().item()) for r in records)) / K
     alg = state + sum(io_bytes_per_frame(sp.npix, sp.rgb, sp.depth, sp.rgb and sp.depth) for sp in wl.streams)
     achieved = alg / (ms_step / 1e3) / 1e9
+    copy_gbs = device_copy_gbs(alg, stream, reps=20)
     out = {
         "metric": "RGBD GMM pixel-updates/s", "value": value, "unit": "pixel-updates/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -229,7 +245,8 @@ def bench_batch(args) -> int:
                      "kernel": f"rgbd::batch_kernel<{M}, {dtype}, {batch.tuning()[0]}>",
                      "algorithmic_bytes_per_launch": alg, "full_rewrite_bytes_per_launch": full,
                      "full_rewrite_frac": full / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "avg_launch_us": ms_step * 1e3},
+                     "avg_launch_us": ms_step * 1e3,
+                     "device_copy_same_bytes_gbs": copy_gbs},
         "state_bytes": sum(sg.state_bytes() for sg in segs),
     }
     batch.close()
@@ -443,25 +460,6 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
     _abi.gmm_set_traffic_record(seg.handle, None)
 
-    # practical read+write ceiling: a device copy moving the same bytes as one launch
-    copy_gbs = None
-    if not args.host_frames:
-        half = int(alg_bytes_hint(n, mix.M, 4 if wl.state_dtype == "f32" else 2) // 2) // 4 * 4
-        src = torch.empty(half // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        with torch.cuda.stream(stream):
-            for _ in range(5):
-                dst.copy_(src)
-            c0 = torch.cuda.Event(enable_timing=True)
-            c1 = torch.cuda.Event(enable_timing=True)
-            c0.record(stream)
-            for _ in range(200):
-                dst.copy_(src)
-            c1.record(stream)
-        torch.cuda.synchronize()
-        copy_gbs = 2 * half / (c0.elapsed_time(c1) / 200 / 1e3) / 1e9
-        del src, dst
-
     pu_step = (1 if augmented else 2) * n
     value = pu_step * K / (ms_total / 1e3)
     idx = [(W + i) % F for i in range(K)]
@@ -472,6 +470,7 @@ def main(argv=None) -> int:
     # augmented: colour and depth inputs, one mask, no fusion state
     alg_bytes = state_bytes + (n * (3 + 2 + 1 / 8) if augmented else io_bytes_per_frame(n))
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
+    copy_gbs = None if args.host_frames else device_copy_gbs(alg_bytes, stream, reps=200)
 
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC) and not augmented and args.rho == "alpha":
