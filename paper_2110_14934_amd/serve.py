@@ -353,6 +353,8 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         both = (k.modalities & GMM_RGB) and (k.modalities & GMM_DEPTH)
         return [(mk(k.modalities & GMM_RGB), mk(k.modalities & GMM_DEPTH), mk(both)) for _ in range(2)]
 
+    spare: Dict[StreamKind, list] = {}   # mask sets made before the run for the streams that join
+
     def add_stream(now: float) -> bool:
         k = mix[int(rng.choice(len(mix), p=weights))]
         sid = server.join(k.width, k.height, k.modalities)
@@ -360,13 +362,18 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
             return False
         kinds[sid] = k
         next_seq[sid] = int(rng.integers(0, 1 << 20))
-        masks[sid] = mask_set(k)
+        masks[sid] = spare[k].pop() if spare.get(k) else mask_set(k)
         heapq.heappush(heap, (now + rng.uniform(0, 1.0 / fps), sid))
         return True
 
     for _ in range(n_streams):
         if not add_stream(t0):
             break
+    # pinned host memory is slow to allocate (pages are locked and mapped for the device): the
+    # mask buffers of every stream that may join during the run are made now
+    n_joins = int(math.ceil(churn_per_s * duration_s)) + 1 if churn_per_s > 0 else 0
+    for k in mix:
+        spare[k] = [mask_set(k) for _ in range(n_joins)]
     start = server.x.now()
     # the initial streams' first arrivals count from the start of the run, not from before the
     # joins (which allocate and initialise state for every stream)
@@ -380,6 +387,7 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
     lat_t: List[float] = []       # arrival time of each measured frame, from the start
     drops_at: List[int] = []      # server drop count at each whole second of the run
     gap_max: List[float] = []     # longest pass of the loop below in each second of the run
+    churn_s: List[float] = []     # time spent in leaves and joins in each second of the run
     prev = start
     pu_done = 0
     frames_done = 0
@@ -391,17 +399,22 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         while len(drops_at) <= int(now - start):
             drops_at.append(server.stats["dropped"])
             gap_max.append(0.0)
+            churn_s.append(0.0)
         gap_max[int(now - start)] = max(gap_max[int(now - start)], now - prev)
         prev = now
         # churn: one stream leaves and one joins per period (joins retried until admitted)
+        churned = pending_joins > 0
         if now >= next_churn:
             live = [s for s in server.streams if not server.streams[s].leaving]
             if live:
                 server.leave(int(rng.choice(live)))
             pending_joins += 1
             next_churn += 1.0 / churn_per_s
+            churned = True
         while pending_joins and add_stream(now):
             pending_joins -= 1
+        if churned:
+            churn_s[int(now - start)] += server.x.now() - now
         # arrivals due
         while heap and heap[0][0] <= now:
             t_arr, sid = heapq.heappop(heap)
@@ -424,8 +437,10 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
                 frames_done += 1
         if progress and now - last_report >= 5.0:
             last_report = now
+            # counts only: a percentile over every latency so far would hold the loop up for
+            # milliseconds as the list grows
             progress(f"t={now - start:5.1f}s streams={len(server.streams)} in_flight={server.in_flight()} "
-                     f"done={frames_done} p99={percentile(lat, 99) * 1e3:.1f}ms")
+                     f"done={frames_done} dropped={server.stats['dropped']}")
     window = end - measure_from
     server.x.drain()
     server.collect()
@@ -440,7 +455,8 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         dropped = drops_at[min(sec + 1, len(drops_at) - 1)] - drops_at[min(sec, len(drops_at) - 1)]
         timeline.append({"t": sec, "frames": int(sel.size), "dropped": int(dropped),
                          "p99_ms": round(float(np.percentile(sel, 99)) * 1e3, 3) if sel.size else None,
-                         "loop_max_ms": round(gap_max[sec] * 1e3, 3) if sec < len(gap_max) else None})
+                         "loop_max_ms": round(gap_max[sec] * 1e3, 3) if sec < len(gap_max) else None,
+                         "churn_ms": round(churn_s[sec] * 1e3, 3) if sec < len(churn_s) else None})
     return {
         "streams_target": n_streams,
         "streams_end": len(server.streams),
