@@ -1,8 +1,9 @@
 // Device-side building blocks of the per-pixel mixture step (gfx950, wave64).
 //
-// One lane owns one pixel of one modality. Its M components are loaded from structure-of-
-// arrays planes (one plane per parameter and rank, so a wave's 64 lanes read 64 consecutive
-// values), advanced one frame in fp32 registers, re-sorted in registers and written back.
+// One lane owns one pixel of one modality. Its M components are loaded from the tiled state
+// layout (below: per tile of 64 pixels, rows of 16-byte chunks shared by the wave's lanes, then
+// each lane's remaining values contiguous), advanced one frame in fp32 registers, re-sorted in
+// registers and written back.
 // Every kernel of the library (plain, fused, batched) calls the same functions below, so all
 // of them produce bit-identical results for the same pixel.
 #pragma once

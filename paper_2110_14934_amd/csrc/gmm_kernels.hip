@@ -4,8 +4,9 @@
 // its foreground bits form exactly one uint64 word of the output mask (one ballot, one store).
 // The interleaved RGB8 input of a wave (192 contiguous bytes when rows are dense) is staged
 // through LDS with 48 dword loads and de-interleaved on chip - the structure-of-arrays split of
-// the colour image done without a separate pass. State planes are structure-of-arrays, so every
-// state load and store of a wave is one contiguous 256-byte (fp32) segment.
+// the colour image done without a separate pass. The state is tiled per wave: a chunk-row load
+// or store of a wave moves 1 KB of contiguous memory, and a pixel's remaining values are
+// contiguous.
 #include <hip/hip_runtime.h>
 
 #include "gmm_device.hpp"
