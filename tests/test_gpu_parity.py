@@ -186,6 +186,20 @@ def test_lockstep_odd_shapes_pitched(w, h, M):
     _lockstep(spec, mix, 12, pitch_pad=5)
 
 
+@pytest.mark.parametrize("kw", [
+    dict(alpha=1.0, w_init=1.0),       # full replacement: every unmatched weight decays to 0
+    dict(k=0.01),                      # almost nothing matches: the last rank is replaced each frame
+    dict(T=1e-3),                      # B = 1: only rank 0 is background
+    dict(T=0.999),                     # B = M for most pixels
+    dict(alpha=1e-4, w_init=1e-4),     # very slow learning
+    dict(hole_skip=False),             # depth 0 is a distance like any other value
+], ids=["alpha1", "k_tiny", "T_tiny", "T_near1", "alpha_tiny", "holes_as_values"])
+def test_lockstep_degenerate_parameters(kw):
+    spec = StreamSpec(96, 40, n_boxes=2, box_min=6, box_max=12, hole_p=0.1, seed=77)
+    say(f"lockstep degenerate {kw}")
+    _lockstep(spec, MixtureSettings(M=4, **kw), 10)
+
+
 def test_lockstep_misaligned_rgb_base():
     spec = StreamSpec(128, 8, n_boxes=1, box_min=4, box_max=6, hole_p=0.05, seed=4242)
     _lockstep(spec, MixtureSettings(M=3, alpha=0.05, w_init=0.05), 8, misalign=True)
