@@ -288,8 +288,9 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
 }
 
 // Values [0, LIMIT) of pixel p from the Mix (whole chunk rows and the whole suffix, as load_mix
-// reads them).
-template <int M, int C, typename S, int LIMIT = (C + 2) * M>
+// reads them). ROWS / SUFFIX select the parts written, so that a caller can store the chunk rows
+// of every lane with one instruction per row and the suffix of some lanes only.
+template <int M, int C, typename S, int LIMIT = (C + 2) * M, bool ROWS = true, bool SUFFIX = true>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
   constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
   constexpr TileLayout L = tile_layout(M, C, es);
@@ -304,7 +305,7 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
   };
   static_for<0, npc>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (c * vpc < LIMIT) {
+    if constexpr (ROWS && c * vpc < LIMIT) {
       u32x4 w = {0u, 0u, 0u, 0u};
       static_for<0, 4>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
@@ -313,7 +314,7 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
       __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
     }
   });
-  if constexpr (LIMIT > nf && nw > 0) {
+  if constexpr (SUFFIX && LIMIT > nf && nw > 0) {
     const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
@@ -332,6 +333,28 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
       __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, sbase + 4u * wi, 0, 0);
     });
   }
+}
+
+// The chunk rows c with c * vpc >= FROM of pixel p from the Mix: the rows a row store of values
+// [0, FROM) leaves out.
+template <int M, int C, typename S, int FROM>
+__device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+  constexpr int es = sizeof(S), vpw = 4 / es;
+  constexpr TileLayout L = tile_layout(M, C, es);
+  constexpr int vpc = L.vpc, npc = L.npc;
+  const uint32_t lane = p & 63u;
+  const uint32_t base = (p >> 6) * b.tile_bytes;
+  static_for<0, npc>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    if constexpr (c * vpc >= FROM) {
+      u32x4 w = {0u, 0u, 0u, 0u};
+      static_for<0, 4>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        w[i] = BufIO<S>::word(field<M, C, c * vpc + i * vpw>(m), field<M, C, c * vpc + i * vpw + vpw - 1>(m));
+      });
+      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
+    }
+  });
 }
 
 // The matched component's new mean, variance and weight (from the values before the update and
