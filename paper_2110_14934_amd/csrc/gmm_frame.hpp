@@ -73,26 +73,21 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   constexpr int NR = static_cast<int>(L.npc * L.vpc);  // values held by the chunk rows
   bool fg = false;
   const bool slow = active && !fast_step<M, C>(m, x, k);
-  Mix<M, C> full = m;
-  if (slow) {
-    load_mix<M, C, S, NV>(full, blk, p);
+  if (slow) {  // m now holds each lane's own path's values
+    load_mix<M, C, S, NV>(m, blk, p);
     int j, q;
-    fg = mix_step<M, C>(full, x, k, j, q);
+    fg = mix_step<M, C>(m, x, k, j, q);
   }
   // Write-back: every piece both paths write goes out in one store for all the lanes that write
-  // it (a 1 KB chunk row then leaves the wave as one write, not as one per path), each lane with
-  // its own path's values. Both paths write the chunk rows the fast prefix covers; when the fast
-  // store reaches into the suffix (the rows cannot hold the prefix), both write the suffix too.
-  // Rows past the prefix, and otherwise the suffix, are the general path's alone.
+  // it (a 1 KB chunk row then leaves the wave as one write, not as one per path). Both paths
+  // write the chunk rows the fast prefix covers; when the fast store reaches into the suffix
+  // (the rows cannot hold the prefix), both write the suffix too. Rows past the prefix, and
+  // otherwise the suffix, are the general path's alone.
   constexpr bool kSuffixShared = SF > NR;
-  static_for<0, (kSuffixShared ? NV : NR)>([&](auto v_) RGBD_BODY {
-    constexpr int v = RGBD_I(v_);
-    field<M, C, v>(m) = pick(slow, field<M, C, v>(full), field<M, C, v>(m));
-  });
   if (valid) store_mix<M, C, S, SF, true, kSuffixShared>(m, blk, p);
   if (slow) {
-    if constexpr (((SF + L.vpc - 1) / L.vpc) * L.vpc < NR) store_rows_from<M, C, S, SF>(full, blk, p);
-    if constexpr (!kSuffixShared) store_mix<M, C, S, NV, false, true>(full, blk, p);
+    if constexpr (((SF + L.vpc - 1) / L.vpc) * L.vpc < NR) store_rows_from<M, C, S, SF>(m, blk, p);
+    if constexpr (!kSuffixShared) store_mix<M, C, S, NV, false, true>(m, blk, p);
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
   wave_bytes += (n_valid - n_slow) * ((prefix_bytes<M, C, LF, S>() + prefix_bytes<M, C, SF, S>()) / kWave) +
