@@ -287,6 +287,49 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
   }
 }
 
+// The values of pixel p that a load of [0, LF) did not bring: the chunk rows from the first one
+// starting at or past LF, and the suffix unless that load read it. With load_mix<LF> before it,
+// the Mix holds the whole state.
+template <int M, int C, typename S, int LF>
+__device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr TileLayout L = tile_layout(M, C, es);
+  constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
+  const uint32_t lane = p & 63u;
+  const uint32_t base = (p >> 6) * b.tile_bytes;
+  static_for<0, npc>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    if constexpr (c * vpc >= LF) {
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
+      static_for<0, vpc>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        field<M, C, c * vpc + i>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
+      });
+    }
+  });
+  if constexpr (LF <= nf && nw > 0) {
+    const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
+    static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
+      constexpr int g = RGBD_I(g_);
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, sbase + 16u * g, 0, 0);
+      static_for<0, 4 * vpw>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        constexpr int v = nf + (4 * g) * vpw + i;
+        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
+      });
+    });
+    static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
+      constexpr int wi = RGBD_I(w_);
+      const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, sbase + 4u * wi, 0, 0);
+      static_for<0, vpw>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        constexpr int v = nf + wi * vpw + i;
+        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w, i);
+      });
+    });
+  }
+}
+
 // Values [0, LIMIT) of pixel p from the Mix (whole chunk rows and the whole suffix, as load_mix
 // reads them). ROWS / SUFFIX select the parts written, so that a caller can store the chunk rows
 // of every lane with one instruction per row and the suffix of some lanes only.

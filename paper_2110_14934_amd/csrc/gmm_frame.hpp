@@ -72,9 +72,11 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   constexpr TileLayout L = tile_layout(M, C, sizeof(S));
   constexpr int NR = static_cast<int>(L.npc * L.vpc);  // values held by the chunk rows
   bool fg = false;
+  const Mix<M, C> read = m;  // the prefix as read (fast_step updates m in place)
   const bool slow = active && !fast_step<M, C>(m, x, k);
   if (slow) {  // m now holds each lane's own path's values
-    load_mix<M, C, S, NV>(m, blk, p);
+    m = read;
+    load_rest<M, C, S, LF>(m, blk, p);
     int j, q;
     fg = mix_step<M, C>(m, x, k, j, q);
   }
