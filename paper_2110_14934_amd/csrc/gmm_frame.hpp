@@ -10,32 +10,56 @@
 
 namespace rgbd {
 
-// Colour pixel p of the frame. When rows are dense and the whole wave is inside the frame, the
-// wave's 192 interleaved bytes are fetched with 48 dword loads into the wave's LDS slice and
-// de-interleaved from there; otherwise each lane reads its own three bytes.
-__device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base,
-                                               int lane, uint32_t* lds_wave, bool valid,
-                                               float (&x)[3]) {
-  const bool fast = a.rgb_dense && (wave_base + kWave <= a.npix);  // uniform over the wave
-  if (fast) {
+// Colour pixel p of the frame, in two halves so that other loads can be issued between them.
+// When rows are dense and the whole wave is inside the frame (uniform over the wave), the wave's
+// 192 interleaved bytes are fetched as 48 dwords (lanes 48-63 repeat the last one), staged in
+// the wave's LDS slice and de-interleaved from there; otherwise each lane reads its own three
+// bytes. `p` must be inside the frame.
+struct RgbLoad {
+  bool staged;
+  uint32_t w;           // staged: this lane's dword of the wave's bytes
+  uint32_t b0, b1, b2;  // per lane: the pixel's bytes
+};
+
+__device__ __forceinline__ RgbLoad issue_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base, int lane) {
+  RgbLoad r{};
+  r.staged = a.rgb_dense && (wave_base + kWave <= a.npix);
+  if (r.staged) {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.rgb + 3 * static_cast<uint64_t>(wave_base));
-    if (lane < 48) lds_wave[lane] = src[lane];
+    r.w = src[lane < 48 ? lane : 47];
+  } else {
+    const uint32_t y = p / static_cast<uint32_t>(a.width);
+    const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
+    const uint8_t* b = a.rgb + static_cast<int64_t>(y) * a.rgb_pitch + 3 * xx;
+    r.b0 = b[0];
+    r.b1 = b[1];
+    r.b2 = b[2];
+  }
+  return r;
+}
+
+__device__ __forceinline__ void finish_rgb_pixel(const RgbLoad& r, int lane, uint32_t* lds_wave, float (&x)[3]) {
+  if (r.staged) {
+    if (lane < 48) lds_wave[lane] = r.w;
     wave_lds_sync();
     const uint8_t* b = reinterpret_cast<const uint8_t*>(lds_wave) + 3 * lane;
     x[0] = b[0];
     x[1] = b[1];
     x[2] = b[2];
     wave_lds_sync();  // the slice is reused by the wave's next pixels
-  } else if (valid) {
-    const uint32_t y = p / static_cast<uint32_t>(a.width);
-    const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
-    const uint8_t* b = a.rgb + static_cast<int64_t>(y) * a.rgb_pitch + 3 * xx;
-    x[0] = b[0];
-    x[1] = b[1];
-    x[2] = b[2];
   } else {
-    x[0] = x[1] = x[2] = 0.f;
+    x[0] = static_cast<float>(r.b0);
+    x[1] = static_cast<float>(r.b1);
+    x[2] = static_cast<float>(r.b2);
   }
+}
+
+// Colour pixel p, both halves at once (the four-channel path); lanes past the end read zeros.
+__device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base, int lane,
+                                               uint32_t* lds_wave, bool valid, float (&x)[3]) {
+  const RgbLoad r = issue_rgb_pixel(a, valid ? p : a.npix - 1, wave_base, lane);
+  finish_rgb_pixel(r, lane, lds_wave, x);
+  if (!valid) x[0] = x[1] = x[2] = 0.f;
 }
 
 __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p) {
@@ -126,16 +150,21 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   const StateBlock blk_d = make_block(a.st_depth, a.tiles64, tile_layout(M, 1, sizeof(S)).bytes);
   Mix<M, 3> mc;
   Mix<M, 1> md;
-  float xd = 0.f;
-  uint32_t fst = 0;
-  // every load of the pixel is issued before any result is used (the state blocks, the fusion
-  // bytes and the frames do not overlap), so a wave waits for memory once, not once per step
-  if (do_c) load_prefix<M, 3, S>(mc, blk_c, p, valid);
-  if (do_d) load_prefix<M, 1, S>(md, blk_d, p, valid);
-  if (do_d && valid) xd = load_depth_pixel(a, p);
-  if (do_f && valid) fst = a.fstate[p];
-  float x[3];
-  if (do_c) load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x);
+  // Every load of the pixel is issued before any result is used (the state blocks, the fusion
+  // bytes and the frames do not overlap), so a wave waits for memory once, not once per step.
+  // The frame bytes and the fusion byte go first and none of them sits behind a per-lane branch
+  // (a lane past the end reads the last pixel instead, and writes nothing): memory results
+  // count down in issue order, so the wait for the colour bytes, which the LDS staging needs at
+  // once, covers only them while the state prefixes stay in flight.
+  const uint32_t pc = valid ? p : a.npix - 1;
+  RgbLoad rl{};
+  if (do_c) rl = issue_rgb_pixel(a, pc, wave_base, lane);
+  const float xd = do_d ? load_depth_pixel(a, pc) : 0.f;
+  const uint32_t fst = do_f ? a.fstate[pc] : 0u;
+  if (do_c) load_mix<M, 3, S, kFastLoad<M, 3>>(mc, blk_c, pc);
+  if (do_d) load_mix<M, 1, S, kFastLoad<M, 1>>(md, blk_d, pc);
+  float x[3] = {0.f, 0.f, 0.f};
+  if (do_c) finish_rgb_pixel(rl, lane, lds_wave, x);
   if (do_c) {
     fgc = step_modality<M, 3, S>(mc, blk_c, p, valid, valid, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fgc);
