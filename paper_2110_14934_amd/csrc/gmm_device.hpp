@@ -400,6 +400,66 @@ __device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateB
   });
 }
 
+// Whether values [a, e) include one of rank r's (its variance or a mean).
+template <int M, int C>
+__host__ __device__ constexpr bool holds_rank(int a, int e, int r) {
+  const int lo = M + r * (C + 1);
+  return lo < e && lo + C + 1 > a;
+}
+
+// Suffix bytes one lane writes with store_suffix_of when only rank r changed there.
+template <int M, int C, typename S>
+__host__ __device__ constexpr uint32_t suffix_rank_bytes(int r) {
+  constexpr int vpw = 4 / static_cast<int>(sizeof(S));
+  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
+  constexpr int nf = L.npc * L.vpc, nw = L.sb / 4;
+  uint32_t n = 0;
+  for (int g = 0; g < nw / 4; ++g) n += holds_rank<M, C>(nf + 4 * g * vpw, nf + (4 * g + 4) * vpw, r) ? 16u : 0u;
+  for (int wi = (nw / 4) * 4; wi < nw; ++wi) n += holds_rank<M, C>(nf + wi * vpw, nf + (wi + 1) * vpw, r) ? 4u : 0u;
+  return n;
+}
+
+// The suffix of pixel p from the Mix, piece by piece as store_mix cuts it (16-byte groups, then
+// words): every piece when `all`, else only the pieces holding a value of rank r. After a frame
+// in which the updated component kept its rank r, only the weights (in the chunk rows) and rank
+// r changed: any other piece would rewrite the bits it holds, and each piece is one more write
+// request of a lane.
+template <int M, int C, typename S>
+__device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool all, int r) {
+  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr TileLayout L = tile_layout(M, C, es);
+  constexpr int npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
+  const uint32_t lane = p & 63u;
+  const uint32_t sbase = (p >> 6) * b.tile_bytes + npc * kRowBytes + lane * L.sb;
+  const int lo = M + r * (C + 1), hi = lo + C + 1;
+  auto sv = [&](auto v_) RGBD_BODY -> float {
+    constexpr int v = RGBD_I(v_);
+    if constexpr (v < NV) return field<M, C, v>(m);
+    else return 0.f;
+  };
+  static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
+    constexpr int g = RGBD_I(g_);
+    constexpr int a = nf + 4 * g * vpw, e = nf + (4 * g + 4) * vpw;
+    if (all | ((lo < e) & (hi > a))) {
+      u32x4 w = {0u, 0u, 0u, 0u};
+      static_for<0, 4>([&](auto i_) RGBD_BODY {
+        constexpr int i = RGBD_I(i_);
+        constexpr int v = nf + (4 * g + i) * vpw;
+        w[i] = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+      });
+      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, sbase + 16u * g, 0, 0);
+    }
+  });
+  static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
+    constexpr int wi = RGBD_I(w_);
+    constexpr int v = nf + wi * vpw;
+    if (all | ((lo < v + vpw) & (hi > v))) {
+      const uint32_t w = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+      __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, sbase + 4u * wi, 0, 0);
+    }
+  });
+}
+
 // The matched component's new mean, variance and weight (from the values before the update and
 // the squared distance d2j of x to its mean); shared by mix_step and fast_step.
 template <int C>

@@ -98,26 +98,39 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   bool fg = false;
   const Mix<M, C> read = m;  // the prefix as read (fast_step updates m in place)
   const bool slow = active && !fast_step<M, C>(m, x, k);
+  int kept = -1;  // the rank the updated component kept, or -1 when the ranks were reordered
   if (slow) {  // m now holds each lane's own path's values
     m = read;
     load_rest<M, C, S, LF>(m, blk, p);
     int j, q;
     fg = mix_step<M, C>(m, x, k, j, q);
+    kept = (j < M ? j : M - 1) == q ? q : -1;
   }
   // Write-back: every piece both paths write goes out in one store for all the lanes that write
   // it (a 1 KB chunk row then leaves the wave as one write, not as one per path). Both paths
   // write the chunk rows the fast prefix covers; when the fast store reaches into the suffix
   // (the rows cannot hold the prefix), both write the suffix too. Rows past the prefix, and
-  // otherwise the suffix, are the general path's alone.
+  // otherwise the suffix, are the general path's alone; of the suffix, a lane whose updated
+  // component kept its rank writes only the pieces holding that rank.
   constexpr bool kSuffixShared = SF > NR;
   if (valid) store_mix<M, C, S, SF, true, kSuffixShared>(m, blk, p);
   if (slow) {
     if constexpr (((SF + L.vpc - 1) / L.vpc) * L.vpc < NR) store_rows_from<M, C, S, SF>(m, blk, p);
-    if constexpr (!kSuffixShared) store_mix<M, C, S, NV, false, true>(m, blk, p);
+    if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, kept < 0, kept);
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
-  wave_bytes += (n_valid - n_slow) * ((prefix_bytes<M, C, LF, S>() + prefix_bytes<M, C, SF, S>()) / kWave) +
-                n_slow * (2u * prefix_bytes<M, C, NV, S>() / kWave);
+  constexpr uint32_t kFull = prefix_bytes<M, C, NV, S>() / kWave;  // a lane's whole state
+  wave_bytes += (n_valid - n_slow) * ((prefix_bytes<M, C, LF, S>() + prefix_bytes<M, C, SF, S>()) / kWave);
+  if constexpr (kSuffixShared) {
+    wave_bytes += n_slow * 2u * kFull;
+  } else {
+    // read everything; write the rows, and the whole suffix or rank `kept`'s pieces of it
+    wave_bytes += n_slow * (kFull + L.npc * kChunkBytes) + __popcll(__ballot(slow && kept < 0)) * L.sb;
+    static_for<0, M>([&](auto r_) RGBD_BODY {
+      constexpr int r = RGBD_I(r_);
+      wave_bytes += __popcll(__ballot(slow && kept == r)) * suffix_rank_bytes<M, C, S>(r);
+    });
+  }
   return fg;
 }
 
