@@ -422,6 +422,29 @@ def test_error_paths_on_device():
         seg.close()
 
 
+def test_traffic_record_counts_only_the_changed_pieces():
+    """Colour only, M=3, fp32: a lane's 15 values are 2 chunk rows (weights, rank 0, rank 1's
+    variance) and a 28-byte suffix (rank 1's means, rank 2) written as one 16-byte group and three
+    words. Frame 0 creates a component that walks from the last rank to rank 0: the whole state
+    is read and written (2 x 60 B). Frame 1 matches rank 0 (fast path: 2 rows read, 2 written,
+    64 B). Frame 2 (x = 250) matches nothing; the new component takes rank 2 and walks to rank 1:
+    reordered, 120 B. Frames 3 and 4 match rank 1, which keeps its rank (the oracle's j = q = 1):
+    60 B read, the rows and the one suffix group holding rank 1 written (32 + 16 B)."""
+    seg = Segmenter(64, 1, GMM_RGB, 3)
+    rec = torch.zeros(1, dtype=torch.int64, device=DEV)
+    try:
+        _abi.gmm_set_traffic_record(seg.handle, rec)
+        want = 0
+        for v, lane_bytes in ((100, 120), (100, 64), (250, 120), (250, 108), (250, 108)):
+            seg.apply(torch.full((1, 64, 3), v, dtype=torch.uint8, device=DEV))
+            torch.cuda.synchronize()
+            want += 64 * lane_bytes
+            assert int(rec[0]) == want, (v, lane_bytes, int(rec[0]), want)
+    finally:
+        _abi.gmm_set_traffic_record(seg.handle, None)
+        seg.close()
+
+
 def test_traffic_record_counts_fast_and_full_lanes():
     """Traffic is decided per lane. Frame 0 matches nothing: every colour lane reads and writes its
     whole state (2 x 25 values x 4 B = 200 B), every depth lane with a reading too (2 x 15 x 4 B =
