@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -35,10 +36,19 @@ FRAME_KERNEL_SOURCES = ("csrc/gmm_device.hpp", "csrc/gmm_frame.hpp", "csrc/gmm_i
 
 
 def kernel_source_digest() -> str:
+    """Hash of the kernel's code: the sources with their comments and blank lines removed, so a
+    change of wording alone does not count as a new kernel."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2110_14934_amd")
     for f in FRAME_KERNEL_SOURCES:
-        h.update(open(os.path.join(pkg, f), "rb").read())
+        text = open(os.path.join(pkg, f), encoding="utf-8").read()
+        if f.endswith(".py"):
+            text = re.sub(r"(?m)^\s*#.*$", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        text = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 

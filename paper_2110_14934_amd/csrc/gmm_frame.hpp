@@ -71,20 +71,23 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
   return static_cast<float>(row[xx]);
 }
 
-// One modality of pixel p, with lazy state traffic decided lane by lane. load_prefix reads only
-// the values a frame needs when the pixel matches its rank-0 component and that component keeps
-// its rank (all weights, rank 0, rank 1's variance); step_modality runs fast_step, the step
-// specialised to that case, on them. A lane for which that held writes back only the weights
-// and rank 0. Any other lane reads its whole state, runs the full step from the original values
-// and writes everything. fast_step computes exactly what the full step computes for such a
-// pixel, so results never depend on which path ran. `valid` lanes hold a pixel; `active` lanes update
-// it (a depth hole is valid but not active: it writes back what it read). Returns the
-// foreground bit; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
+// The values a frame needs when the pixel matches its rank-0 component and that component keeps
+// its rank: all weights, rank 0 and rank 1's variance (the fast-path prefix, in the chunk rows).
 template <int M, int C, typename S>
 __device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid) {
   if (valid) load_mix<M, C, S, kFastLoad<M, C>>(m, blk, p);
 }
 
+// One modality of pixel p, with lazy state traffic decided lane by lane, on the prefix in `m`.
+// fast_step is the step specialised to the case above; a lane for which that case holds writes
+// back only the weights and rank 0. Any other lane keeps the prefix as read, loads the rest of
+// its state, runs the full step from the original values and writes back what changed: the
+// chunk rows, and the whole suffix when the ranks were reordered, else only the suffix pieces
+// of the rank the updated component kept. fast_step computes exactly what the full step
+// computes for such a pixel, so results never depend on which path ran. `valid` lanes hold a
+// pixel; `active` lanes update it (a depth hole is valid but not active: it writes back what it
+// read). Returns the foreground bit; adds the state bytes the wave's lanes read and wrote to
+// `wave_bytes`.
 template <int M, int C, typename S>
 __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
                                               bool active, const float (&x)[C], const ModelConsts& k,
