@@ -344,7 +344,7 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py runs on one GPU only: there is no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         return 2
     if args.workload in ("batch-64", "precision-256"):

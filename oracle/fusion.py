@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.
 
 Per pixel the rule keeps a fused bit I and an integer counter cpt (both persistent across
-frames; both start at 0 in this build). With r, d the colour and depth foreground bits:
+frames; both start at 0 here). With r, d the colour and depth foreground bits:
   * r == d: I takes the common value and the counter resets;
   * r != d and cpt == +3: I takes the colour bit, counter reset;
   * r != d and cpt == -3: I takes the depth bit, counter reset;
