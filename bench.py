@@ -36,8 +36,8 @@ FRAME_KERNEL_SOURCES = ("csrc/gmm_device.hpp", "csrc/gmm_frame.hpp", "csrc/gmm_i
 
 
 def kernel_source_digest() -> str:
-    """Hash of the kernel's code: the sources with their comments and blank lines removed, so a
-    change of wording alone does not count as a new kernel."""
+    """Hash of the kernel's code: the sources with comments, blank lines and the whitespace around
+    each line removed, so a change of wording alone does not count as a new kernel."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2110_14934_amd")
     for f in FRAME_KERNEL_SOURCES:
@@ -47,7 +47,7 @@ def kernel_source_digest() -> str:
         else:
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
             text = re.sub(r"//[^\n]*", "", text)
-        text = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        text = "\n".join(line.strip() for line in text.splitlines() if line.strip())
         h.update(text.encode())
     return h.hexdigest()[:16]
 

@@ -1,0 +1,36 @@
+"""bench.kernel_source_digest: the counter-measured traffic is reported only while the kernel's
+code hashes to the value recorded with the counters; wording in comments must not change the
+hash, code must."""
+import os
+
+import bench
+
+
+def _digest_of(tmp_path, monkeypatch, texts):
+    pkg = tmp_path / "paper_2110_14934_amd"
+    (pkg / "csrc").mkdir(parents=True)
+    names = []
+    for name, text in texts.items():
+        (pkg / name).write_text(text)
+        names.append(name)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "FRAME_KERNEL_SOURCES", tuple(names))
+    return bench.kernel_source_digest()
+
+
+def test_comments_do_not_change_the_digest_code_does(tmp_path, monkeypatch):
+    base = {"csrc/k.hip": "int f(int x) {\n  return x + 1;\n}\n", "build.py": "FLAGS = ['-O3']\n"}
+    d0 = _digest_of(tmp_path / "a", monkeypatch, base)
+    commented = {"csrc/k.hip": "// one more\nint f(int x) {  // add one\n  /* block\n comment */ return x + 1;\n}\n\n",
+                 "build.py": "# flags\nFLAGS = ['-O3']\n"}
+    assert _digest_of(tmp_path / "b", monkeypatch, commented) == d0
+    changed = {"csrc/k.hip": "int f(int x) {\n  return x + 2;\n}\n", "build.py": "FLAGS = ['-O3']\n"}
+    assert _digest_of(tmp_path / "c", monkeypatch, changed) != d0
+    flags = {"csrc/k.hip": "int f(int x) {\n  return x + 1;\n}\n", "build.py": "FLAGS = ['-O2']\n"}
+    assert _digest_of(tmp_path / "d", monkeypatch, flags) != d0
+
+
+def test_recorded_traffic_matches_the_current_kernel():
+    import json
+    rec = json.load(open(os.path.join(bench.ROOT, "profiles", "traffic_frame_kernel_plain-640x480.json")))
+    assert rec["kernel_source_digest"] == bench.kernel_source_digest()
