@@ -199,6 +199,16 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream);
  */
 gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream);
 
+/*
+ * Device-side snapshot of the state, for rolling a handle back (replaying the same frames from
+ * the same state, trial launches): copies gmm_state_bytes bytes of the state, in the library's
+ * own device layout, to (save) or from (restore) the caller's device buffer `device_dst` /
+ * `device_src` (any alignment; owned by the caller; restore takes only a buffer a save of a
+ * handle with the same configuration filled). Asynchronous on `stream`.
+ */
+gmm_status gmm_state_save(gmm_handle* h, void* device_dst, void* stream);
+gmm_status gmm_state_restore(gmm_handle* h, const void* device_src, void* stream);
+
 /* ---- batched path: many streams, one persistent launch per frame-set --------------------- */
 
 typedef struct gmm_batch gmm_batch;
@@ -353,6 +363,15 @@ double gmm_exec_now(void);
  */
 gmm_status gmm_mask_confusion(const uint64_t* pred, const uint64_t* truth, int64_t npix, uint64_t* counts,
                               void* stream);
+
+/*
+ * Measurement aid: copy `bytes` bytes from device `src` to device `dst` (both 16-byte aligned,
+ * not overlapping) with the library's streaming copy kernel, asynchronously on `stream`. It reads
+ * and writes exactly `bytes` each, which makes it the yardstick of the memory system's practical
+ * read+write rate beside the mixture kernels and the calibration of the HBM traffic counters.
+ * No allocation.
+ */
+gmm_status gmm_device_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t gmm_version(void);

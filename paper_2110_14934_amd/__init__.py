@@ -15,7 +15,8 @@ from ._abi import (GMM_RGB, GMM_DEPTH, GMM_F32, GMM_F16, GMM_BF16, GMM_HOLE_SKIP
                    gmm_fuse, gmm_apply_frame_fused, gmm_last_error, gmm_state_bytes, gmm_state_size,
                    gmm_read_state, gmm_write_state, gmm_version, stream_io, gmm_batch_create,
                    gmm_batch_destroy, gmm_batch_set_tuning, gmm_batch_get_tuning, gmm_batch_set_frames,
-                   gmm_batch_run, gmm_batch_apply, gmm_batch_autotune, gmm_batch_tiles)
+                   gmm_batch_run, gmm_batch_apply, gmm_batch_autotune, gmm_batch_tiles,
+                   gmm_state_save, gmm_state_restore, gmm_device_copy)
 
 
 def mask_words(npix: int) -> int:
@@ -88,6 +89,13 @@ class Segmenter:
 
     def state_bytes(self) -> int:
         return gmm_state_bytes(self.handle)
+
+    def save_state(self, device_dst, stream=None):
+        """Device-side snapshot of the state into a caller-owned device tensor."""
+        gmm_state_save(self.handle, device_dst, stream)
+
+    def restore_state(self, device_src, stream=None):
+        gmm_state_restore(self.handle, device_src, stream)
 
     def close(self):
         if self.handle is not None:

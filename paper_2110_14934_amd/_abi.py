@@ -42,6 +42,7 @@ EXPORTS = (
     "gmm_exec_launch", "gmm_exec_poll", "gmm_exec_drain", "gmm_exec_now",
     "gmm_exec_stream_bytes", "gmm_exec_create_stream", "gmm_exec_destroy_stream",
     "gmm_set_traffic_record", "gmm_apply_frame_augmented",
+    "gmm_state_save", "gmm_state_restore", "gmm_device_copy",
 )
 
 
@@ -140,6 +141,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "gmm_exec_destroy_stream": (st, [H, H]),
         "gmm_set_traffic_record": (st, [H, vp]),
         "gmm_apply_frame_augmented": (st, [H, vp, i64, vp, i64, vp, vp]),
+        "gmm_state_save": (st, [H, vp, vp]),
+        "gmm_state_restore": (st, [H, vp, vp]),
+        "gmm_device_copy": (st, [vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -241,6 +245,27 @@ def gmm_write_state(h, state, stream=None):
     if arr.size != gmm_state_size(h):
         raise ValueError(f"state has {arr.size} values, handle needs {gmm_state_size(h)}")
     _check(load().gmm_write_state(h, arr.ctypes.data, _stream(stream)))
+
+
+def gmm_state_save(h, device_dst, stream=None):
+    """device_dst: a device tensor of at least gmm_state_bytes(h) bytes."""
+    if device_dst.numel() * device_dst.element_size() < gmm_state_bytes(h):
+        raise ValueError("snapshot buffer smaller than the state")
+    _check(load().gmm_state_save(h, _ptr(device_dst), _stream(stream)))
+
+
+def gmm_state_restore(h, device_src, stream=None):
+    if device_src.numel() * device_src.element_size() < gmm_state_bytes(h):
+        raise ValueError("snapshot buffer smaller than the state")
+    _check(load().gmm_state_restore(h, _ptr(device_src), _stream(stream)))
+
+
+def gmm_device_copy(dst, src, nbytes: int, stream=None):
+    """Copy nbytes between two device tensors with the library's streaming copy kernel."""
+    for t in (dst, src):
+        if t.numel() * t.element_size() < nbytes:
+            raise ValueError("tensor smaller than the copy")
+    _check(load().gmm_device_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
 
 
 def gmm_version() -> int:

@@ -308,6 +308,27 @@ gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles) {
   return GMM_OK;
 }
 
+// Raw device copies of the state (the device layout, gmm_state_bytes bytes), ordered on `stream`.
+static gmm_status copy_state_raw(gmm_handle* h, void* dst, const void* src, void* stream, const char* what) {
+  DeviceGuard g(h->cfg.device);
+  if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(dst, src, state_bytes(h), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, what);
+  h->last_stream = s;
+  return GMM_OK;
+}
+
+gmm_status gmm_state_save(gmm_handle* h, void* device_dst, void* stream) {
+  if (!h || !device_dst) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  return copy_state_raw(h, device_dst, h->mem, stream, "state save");
+}
+
+gmm_status gmm_state_restore(gmm_handle* h, const void* device_src, void* stream) {
+  if (!h || !device_src) return fail(GMM_ERR_INVALID_ARG, "NULL argument");
+  return copy_state_raw(h, h->mem, device_src, stream, "state restore");
+}
+
 }  // extern "C"
 
 gmm_status rgbd::check_frame_args(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch,

@@ -327,6 +327,18 @@ def percentile(values: Sequence[float], q: float) -> float:
     return float(np.percentile(np.asarray(values), q))
 
 
+def percentile_with_drops(values: Sequence[float], n_dropped: int, q: float) -> float:
+    """Nearest-rank q-th percentile of the latencies with every dropped frame counted as an
+    infinite latency (inf once the dropped share exceeds 100 - q percent)."""
+    n = len(values) + n_dropped
+    if n == 0:
+        return math.nan
+    rank = max(1, int(math.ceil(q / 100.0 * n)))
+    if rank > len(values):
+        return math.inf
+    return float(np.sort(np.asarray(values))[rank - 1])
+
+
 def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams: int, duration_s: float,
              fps: float = 30.0, jitter: float = 0.2, churn_per_s: float = 1.0, seed: int = 211014938,
              mix: Sequence[StreamKind] = SERVE_MIX, warmup_s: float = 1.0, progress=None,
@@ -391,6 +403,7 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
     prev = start
     pu_done = 0
     frames_done = 0
+    arrived_measured = dropped_measured = 0   # arrivals in the measured window, and those refused
     last_report = start
     while True:
         now = server.x.now()
@@ -426,7 +439,10 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
             pool = pools[(k.width, k.height, k.modalities)]
             rgb, dep = pool[seq % len(pool)]
             o = masks[sid][seq & 1]
-            server.submit(FrameRequest(sid, seq, t_arr, rgb, dep, o[0], o[1], o[2]))
+            accepted = server.submit(FrameRequest(sid, seq, t_arr, rgb, dep, o[0], o[1], o[2]))
+            if t_arr >= measure_from:
+                arrived_measured += 1
+                dropped_measured += 0 if accepted else 1
             heapq.heappush(heap, (t_arr + rng.uniform(1 - jitter, 1 + jitter) / fps, sid))
         for req in server.step():
             if req.t_arrival >= measure_from:
@@ -466,6 +482,11 @@ def run_load(server: Server, pools: Dict[Tuple[int, int, int], list], n_streams:
         "pixel_updates_per_s": pu_done / window if window > 0 else math.nan,
         "p50_latency_ms": percentile(lat, 50) * 1e3,
         "p99_latency_ms": percentile(lat, 99) * 1e3,
+        # over every frame that arrived in the window, a dropped one counting as infinitely late
+        "p50_latency_ms_arrivals": percentile_with_drops(lat, dropped_measured, 50) * 1e3,
+        "p99_latency_ms_arrivals": percentile_with_drops(lat, dropped_measured, 99) * 1e3,
+        "arrived_in_window": arrived_measured,
+        "dropped_in_window": dropped_measured,
         "max_latency_ms": (max(lat) * 1e3) if lat else math.nan,
         "stats": dict(server.stats),
         "timeline": timeline,

@@ -14,8 +14,8 @@ def _digest_of(tmp_path, monkeypatch, texts):
         (pkg / name).write_text(text)
         names.append(name)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "FRAME_KERNEL_SOURCES", tuple(names))
-    return bench.kernel_source_digest()
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", {"frame": tuple(names)})
+    return bench.kernel_source_digest("frame")
 
 
 def test_comments_do_not_change_the_digest_code_does(tmp_path, monkeypatch):
@@ -33,4 +33,14 @@ def test_comments_do_not_change_the_digest_code_does(tmp_path, monkeypatch):
 def test_recorded_traffic_matches_the_current_kernel():
     import json
     rec = json.load(open(os.path.join(bench.ROOT, "profiles", "traffic_frame_kernel_plain-640x480.json")))
-    assert rec["kernel_source_digest"] == bench.kernel_source_digest()
+    assert rec["kernel_source_digest"] == bench.kernel_source_digest("frame")
+
+
+def test_clip_plays_forwards_then_backwards_without_a_jump():
+    F = 120
+    seq = [bench.clip_frame(i, F) for i in range(3 * (2 * F - 2) + 7)]
+    assert seq[:F] == list(range(F))
+    assert seq[F:2 * F - 2] == list(range(F - 2, 0, -1))
+    assert all(abs(a - b) == 1 for a, b in zip(seq, seq[1:]))
+    assert set(seq) == set(range(F))
+    assert bench.clip_frame(5, 1) == 0

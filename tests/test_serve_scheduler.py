@@ -317,3 +317,17 @@ def test_failed_launch_leaves_the_server_consistent():
     x.complete_all()
     done = srv.step()
     assert sorted((r.stream_id, r.seq) for r in done) == [(a, 0), (b, 0)]
+
+
+def test_percentile_counts_dropped_frames_as_infinitely_late():
+    import math
+    from paper_2110_14934_amd.serve import percentile_with_drops
+    lat = [float(i) for i in range(1, 101)]          # 1 .. 100
+    assert percentile_with_drops(lat, 0, 99) == 99.0
+    assert percentile_with_drops(lat, 0, 50) == 50.0
+    # one drop among 101 frames: the 99th percentile (rank 100) is still a completed frame
+    assert percentile_with_drops(lat, 1, 99) == 100.0
+    # two drops among 102: rank ceil(0.99 * 102) = 101 lands on a drop
+    assert percentile_with_drops(lat, 2, 99) == math.inf
+    assert math.isnan(percentile_with_drops([], 0, 99))
+    assert percentile_with_drops([], 3, 50) == math.inf
