@@ -45,7 +45,8 @@ _TAG_HOLE = 4
 
 
 def _mix32_int(x: int) -> int:
-    """32-bit avalanche hash (xorshift-multiply, two rounds) on a Python int."""
+    """32-bit avalanche hash on a Python int: two xorshift-multiply rounds with the shifts and
+    multipliers of Chris Wellons' published "lowbias32" integer hash (hash-prospector)."""
     x &= MASK32
     x ^= x >> 16
     x = (x * _C1) & MASK32
