@@ -90,13 +90,24 @@ def test_reduced_precision_report():
             report[d] = r
         print("PRECISION_REPORT " + json.dumps(report), flush=True)
         sys.stdout.flush()
-        # fp32 state matches the oracle to the free-run bound; reduced precision stays usable
-        assert report["f32"]["mask_disagreement_vs_fp64_rgb"] <= 1e-3
-        assert report["f32"]["mask_disagreement_vs_fp64_depth"] <= 1e-3
-        for d in ("f16", "bf16"):
+        # fp32 state matches the oracle to the free-run bar
+        for m in ("rgb", "depth"):
+            assert report["f32"][f"mask_disagreement_vs_fp64_{m}"] <= 1e-4, m
+            assert report["f32"][f"rank0_same_component_{m}"] >= 0.999, m
+            for p in ("mu", "var", "w"):
+                assert report["f32"][f"rank0_{p}_max_rel_err_{m}"] <= 1e-4, (m, p)
+        # reduced precision: about twice what the kernels measured on this clip. Colour means
+        # stagnate (an update below half a storage ulp is lost), so only the masks and the
+        # depth model, whose means sit far above their ulp, are bounded tightly.
+        bounds = {"f16": {"mask_rgb": 2e-3, "mask_depth": 1e-4, "mu_depth": 1e-2, "var_depth": 0.15, "w_depth": 5e-3},
+                  "bf16": {"mask_rgb": 6e-3, "mask_depth": 2e-4, "mu_depth": 1e-2, "var_depth": 0.45, "w_depth": 4e-2}}
+        for d, b in bounds.items():
+            assert report[d]["mask_disagreement_vs_fp64_rgb"] <= b["mask_rgb"], d
+            assert report[d]["mask_disagreement_vs_fp64_depth"] <= b["mask_depth"], d
+            for p in ("mu", "var", "w"):
+                assert report[d][f"rank0_{p}_max_rel_err_depth"] <= b[f"{p}_depth"], (d, p)
             for m in ("rgb", "depth"):
-                assert report[d][f"mask_disagreement_vs_fp64_{m}"] < 0.25, (d, m)
-                assert report[d][f"rank0_same_component_{m}"] > 0.5, (d, m)
+                assert report[d][f"rank0_same_component_{m}"] >= 0.999, (d, m)
     finally:
         for d in dtypes:
             batches[d].close()

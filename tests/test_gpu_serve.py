@@ -32,13 +32,13 @@ def words(sp):
     return (sp.npix + 63) // 64
 
 
-# a frame of several 64 KiB ingest pieces with a ragged last piece
+# a wider frame whose byte counts are not multiples of 64 KiB
 WIDE = StreamSpec(330, 241, n_boxes=2, box_min=20, box_max=40, hole_p=0.02, seed=71, index=4)
 
 
 def host_frame(t, how, k):
-    """Frame t in host memory: pinned (read by the ingest kernel), pageable (copied by DMA), or
-    pinned at an odd offset inside a larger pinned allocation (ingest, unaligned pieces)."""
+    """Frame t in host memory, as the executor's copies meet it: pinned, pageable, or pinned at
+    an odd offset inside a larger pinned allocation (an unaligned source address)."""
     t = t.contiguous()
     if how == "pageable":
         return t.clone()
@@ -273,3 +273,131 @@ def test_short_serving_run():
     assert rep["frames_completed"] > 48 * 30 * 2
     assert rep["p99_latency_ms"] < 33.0
     assert rep["stats"]["dropped"] == 0
+
+
+# ---- served streams against the FP64 oracle ------------------------------------------------
+
+def _serve_and_follow(dtype, T=30):
+    """Three target streams (colour+depth, depth only, colour only) served in a churning mix with
+    two frames per stream in flight; returns per target the masks of every frame and the final
+    state, beside the oracle that stepped the same frames (emulating the storage rounding for
+    16-bit state)."""
+    from oracle import MixParams, MixtureOracle, FusionOracle
+    from tests.parity import unpack_mask
+    targets = [StreamSpec(160, 120, n_boxes=2, box_min=10, box_max=30, hole_p=0.05, seed=74, index=0),
+               StreamSpec(96, 40, rgb=False, depth=True, n_boxes=1, box_min=6, box_max=12, hole_p=0.05, seed=74, index=1),
+               StreamSpec(120, 64, rgb=True, depth=False, n_boxes=2, box_min=8, box_max=20, seed=74, index=2)]
+    tstreams = [Stream(s) for s in targets]
+    frames = [[(pinned(st.rgb(t)) if sp.rgb else None, pinned(st.depth(t)) if sp.depth else None)
+               for t in range(T)] for sp, st in zip(targets, tstreams)]
+    bg = [Stream(StreamSpec(80, 60, n_boxes=1, box_min=5, box_max=15, seed=75, index=i)) for i in range(4)]
+    bg_frames = [[(pinned(o.rgb(t)), pinned(o.depth(t))) for t in range(T)] for o in bg]
+    storage = None if dtype == "f32" else dtype
+    oracles = []
+    for sp in targets:
+        col = MixtureOracle(MixParams(5, 0.01, 2.5, 0.7, 30.0, 9.0, 0.01), 3, sp.npix, storage) if sp.rgb else None
+        dep = (MixtureOracle(MixParams(5, 0.01, 2.5, 0.7, 50.0, 25.0, 0.01, hole_skip=True), 1, sp.npix, storage)
+               if sp.depth else None)
+        oracles.append((col, dep, FusionOracle(sp.npix) if sp.rgb and sp.depth else None))
+    ex = NativeExecutor(ring=3, state_dtype=dtype, arena_bytes=256 << 20)
+    srv = Server(ex, 256 << 20, max_queue=64)
+    masks = [[[torch.zeros(words(sp), dtype=torch.int64).pin_memory() if on else None
+               for on in (sp.rgb, sp.depth, sp.rgb and sp.depth)] for _ in range(T)] for sp in targets]
+    got = {}
+    try:
+        sids = [srv.join(sp.width, sp.height, mods(sp)) for sp in targets]
+        live = [srv.join(80, 60, GMM_RGB | GMM_DEPTH) for _ in range(3)]
+        for t in range(T):
+            for k, (sid, sp) in enumerate(zip(sids, targets)):
+                m = masks[k][t]
+                assert srv.submit(FrameRequest(sid, t, 0.0, frames[k][t][0], frames[k][t][1], m[0], m[1], m[2]))
+            for j, sid in enumerate(live):
+                f = bg_frames[(sid + j) % 4][t]
+                srv.submit(FrameRequest(sid, t, 0.0, f[0], f[1]))
+            if t % 6 == 3:   # churn: one background stream leaves, another joins
+                srv.leave(live.pop(0))
+                live.append(srv.join(80, 60, GMM_RGB | GMM_DEPTH))
+            # two launches per frame period: each stream's next frame goes out before its last
+            # one has completed (two frames per stream on the device)
+            for _ in range(2):
+                for req in srv.step():
+                    got[(req.stream_id, req.seq)] = True
+        for _ in range(200):
+            ex.drain()
+            for req in srv.step():
+                got[(req.stream_id, req.seq)] = True
+            if all((sid, t) in got for sid in sids for t in range(T)):
+                break
+        assert all((sid, t) in got for sid in sids for t in range(T))
+        states = [_abi.gmm_read_state(srv.streams[sid].handle) for sid in sids]
+    finally:
+        srv.close()
+        ex.close()
+    assert srv.stats["ticks"] >= T
+    results = []
+    for k, (sp, st) in enumerate(zip(targets, tstreams)):
+        col, dep, fus = oracles[k]
+        per_frame = []
+        for t in range(T):
+            ic = col.step(st.rgb(t).reshape(-1, 3).numpy()) if col is not None else None
+            idd = dep.step(st.depth(t).reshape(-1).numpy()) if dep is not None else None
+            fo = fus.step(ic.fg, idd.fg) if fus is not None else None
+            m = masks[k][t]
+            per_frame.append((ic, idd, fo, [unpack_mask(w, sp.npix) if w is not None else None for w in m]))
+        results.append((sp, (col, dep, fus), per_frame, states[k]))
+    return results
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_served_streams_follow_the_oracle(dtype):
+    """Served frames against the FP64 oracle in free run. fp32 state: masks equal except at
+    pixels whose decision was within the free-run margins (these count as diverged from then on),
+    parameters within 1e-4 relative elsewhere, differing pixel-frames <= 1e-4. fp16 state: the
+    oracle rounds every stored value to fp16 as the device does; parameters within 4 fp16 ulps
+    (the device computes in fp32, the oracle in fp64, so a value can round the other way when it
+    falls within a few fp32 ulps of an fp16 midpoint, about once in a thousand updates, and such
+    one-ulp steps can add up over a free run; 2 ulps measured), decisions excused within
+    fp16-sized margins."""
+    from tests.parity import (excused, from_canonical, param_mismatch, oracle_state, WEIGHT_MARGIN_FREE,
+                              KEY_GAP_FREE, MASK_FRACTION)
+    from tests.test_gpu_parity import _ulp
+    res = _serve_and_follow(dtype)
+    wm, kg = (WEIGHT_MARGIN_FREE, KEY_GAP_FREE) if dtype == "f32" else (4e-3, 4e-3)
+    dis = total = 0
+    worst_ulps = 0.0
+    for sp, (col, dep, fus), per_frame, state in res:
+        n = sp.npix
+        risky = {"rgb": np.zeros(n, bool), "depth": np.zeros(n, bool)}
+        for t, (ic, idd, fo, (gr, gd, gf)) in enumerate(per_frame):
+            for name, info, g in (("rgb", ic, gr), ("depth", idd, gd)):
+                if info is None:
+                    continue
+                ex = excused(info, wm, kg)
+                if dtype != "f32":
+                    ex |= info.match_margin < 4e-3
+                risky[name] |= ex
+                diff = g != info.fg
+                assert not np.any(diff & ~risky[name]), (sp, name, t, np.flatnonzero(diff & ~risky[name])[:8])
+                dis += int(diff.sum())
+                total += n
+            if fo is not None:
+                assert not np.any((gf != fo) & ~(risky["rgb"] | risky["depth"])), (sp, t)
+        got = from_canonical(state, 5, n, sp.rgb, sp.depth)
+        for name, o in (("rgb", col), ("depth", dep)):
+            if o is None:
+                continue
+            if dtype == "f32":
+                bad = param_mismatch(got[name], oracle_state(o)) & ~risky[name]
+                assert not np.any(bad), (sp, name, np.flatnonzero(bad)[:8])
+            else:
+                for g, ov in zip(got[name], oracle_state(o)):
+                    u = np.abs(g - ov) / _ulp(ov, dtype)
+                    u = u.reshape(-1, n)[:, ~risky[name]]
+                    worst_ulps = max(worst_ulps, float(u.max()) if u.size else 0.0)
+        print(f"SERVE_ORACLE {dtype} {sp.width}x{sp.height} risky rgb {risky['rgb'].mean():.2e} "
+              f"depth {risky['depth'].mean():.2e}", flush=True)
+    print(f"SERVE_ORACLE {dtype}: mask disagreement {dis}/{total} = {dis / total:.2e}, worst non-risky "
+          f"parameter error {worst_ulps:.2f} storage ulps", flush=True)
+    assert dis <= (MASK_FRACTION if dtype == "f32" else 1e-3) * total + 1
+    if dtype != "f32":
+        assert worst_ulps <= 4.0001
