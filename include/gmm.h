@@ -285,6 +285,31 @@ gmm_status gmm_batch_autotune(gmm_batch* b, int32_t slot, void* stream, gmm_batc
 /* Number of tiles of one launch under the current tuning. */
 gmm_status gmm_batch_tiles(const gmm_batch* b, uint32_t* n_tiles);
 
+/* ---- batched launch without allocation ---------------------------------------------------- */
+
+#define GMM_STATIC_MAX_STREAMS 1024
+
+/*
+ * For callers that cannot allocate device memory - code under HIP graph capture, serving loops
+ * and harnesses that forbid hipMalloc: gmm_batch_apply for `n` existing handles (1 ..
+ * GMM_STATIC_MAX_STREAMS; same device, M and state dtype; each at most once) without a
+ * gmm_batch object. `io` is a host array of n stream entries (rules of gmm_batch_set_frames);
+ * `tuning` is the launch shape (NULL: {256, 1024, 8}; limits of gmm_batch_tuning). Per stream,
+ * masks and state are bit-identical to gmm_batch_apply (and so to gmm_apply_frame /
+ * gmm_apply_frame_fused).
+ * The per-call tables (stream descriptors and first tiles, about 212 KB at the maximum) live in
+ * one static device array of the library, one per device, held until the process ends; the call
+ * allocates no memory on the device or through any allocating library routine, and copies
+ * nothing from host memory (the descriptors travel as kernel arguments), so it can be captured.
+ * Every call on a device reuses that device's array, which keeps the last call's contents:
+ * calls that overlap on one device (different streams, or threads without ordering) race and
+ * must be ordered by the caller. More than GMM_STATIC_MAX_STREAMS streams: GMM_ERR_INVALID_ARG
+ * before any device work. GMM_ERR_UNSUPPORTED for a GMM_AUGMENTED handle. Asynchronous on
+ * `stream`.
+ */
+gmm_status gmm_batch_apply_static(gmm_handle* const* handles, int32_t n, const gmm_stream_io* io,
+                                  const gmm_batch_tuning* tuning, void* stream);
+
 /* ---- serving executor: ticks of host frames through one batched launch each --------------- */
 
 typedef struct gmm_exec gmm_exec;

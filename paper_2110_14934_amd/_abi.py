@@ -42,8 +42,9 @@ EXPORTS = (
     "gmm_exec_launch", "gmm_exec_poll", "gmm_exec_drain", "gmm_exec_now",
     "gmm_exec_stream_bytes", "gmm_exec_create_stream", "gmm_exec_destroy_stream",
     "gmm_set_traffic_record", "gmm_apply_frame_augmented",
-    "gmm_state_save", "gmm_state_restore", "gmm_device_copy",
+    "gmm_state_save", "gmm_state_restore", "gmm_device_copy", "gmm_batch_apply_static",
 )
+GMM_STATIC_MAX_STREAMS = 1024
 
 
 class GmmError(RuntimeError):
@@ -144,6 +145,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "gmm_state_save": (st, [H, vp, vp]),
         "gmm_state_restore": (st, [H, vp, vp]),
         "gmm_device_copy": (st, [vp, vp, ctypes.c_size_t, vp]),
+        "gmm_batch_apply_static": (st, [ctypes.POINTER(H), ctypes.c_int32, ctypes.POINTER(gmm_stream_io),
+                                        ctypes.POINTER(gmm_batch_tuning), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -331,6 +334,15 @@ def gmm_batch_autotune(b, slot: int = 0, stream=None):
     ms = ctypes.c_double()
     _check(load().gmm_batch_autotune(b, slot, _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
     return t.as_tuple(), ms.value
+
+
+def gmm_batch_apply_static(handles, ios, tuning=None, stream=None):
+    """One batched launch over `handles` with the library's static tables (no allocation).
+    tuning: (block_threads, tile_pixels, blocks_per_cu) or None for the default."""
+    hs = (ctypes.c_void_p * len(handles))(*handles)
+    arr = (gmm_stream_io * len(ios))(*ios) if ios else None
+    t = None if tuning is None else ctypes.byref(gmm_batch_tuning(*tuning))
+    _check(load().gmm_batch_apply_static(hs, len(handles), arr, t, _stream(stream)))
 
 
 def gmm_batch_tiles(b) -> int:

@@ -137,3 +137,13 @@ def test_augmented_variant_needs_both_modalities_and_runs_alone(lib):
     n = ctypes.c_size_t()
     assert lib.gmm_exec_stream_bytes(ctypes.byref(cfg), ctypes.byref(n)) == _abi.GMM_ERR_UNSUPPORTED
     assert lib.gmm_apply_frame_augmented(None, None, 0, None, 0, None, None) == _abi.GMM_ERR_INVALID_ARG
+
+
+def test_static_batch_rejects_too_many_streams_before_device_work(lib):
+    n = _abi.GMM_STATIC_MAX_STREAMS + 1
+    assert lib.gmm_batch_apply_static(None, n, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert "static descriptor table" in _abi.gmm_last_error()
+    assert lib.gmm_batch_apply_static(None, 0, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    assert lib.gmm_batch_apply_static(None, 1, None, None, None) == _abi.GMM_ERR_INVALID_ARG
+    header = open(HEADER).read()
+    assert f"#define GMM_STATIC_MAX_STREAMS {_abi.GMM_STATIC_MAX_STREAMS}" in header
