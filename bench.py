@@ -526,6 +526,7 @@ def h2d_ceiling(pools, mix, n_streams: int, fps: float = 30.0, copy_streams: int
         pool = pools[(k.width, k.height, k.modalities)]
         plan += [pool[i % len(pool)] for i in range(cnt)]
     nbytes = sum(sum(t.numel() * t.element_size() for t in f if t is not None) for f in plan)
+    npu = sum(sum(t.shape[0] * t.shape[1] for t in f if t is not None) for f in plan)
     big = max(t.numel() * t.element_size() for f in plan for t in f if t is not None)
     dev = torch.device("cuda", 0)
     dst = [torch.empty(big, dtype=torch.uint8, device=dev) for _ in range(copy_streams)]
@@ -545,9 +546,26 @@ def h2d_ceiling(pools, mix, n_streams: int, fps: float = 30.0, copy_streams: int
                 i += 1
         torch.cuda.synchronize()
         best = min(best, time.perf_counter() - t0)
-    return {"ceiling_gbs": nbytes / best / 1e9, "demand_gbs": nbytes * fps / 1e9, "bytes_per_frame_set": nbytes,
-            "streams": len(plan), "copy_streams": copy_streams,
-            "note": "best of 3 rounds of one frame of every stream, pinned host memory, plain async copies"}
+    # the link itself: the same bytes as copy_streams large copies from pinned memory, one per
+    # stream (no per-frame issue cost)
+    part = (nbytes + copy_streams - 1) // copy_streams
+    hsrc = [torch.empty(part, dtype=torch.uint8, pin_memory=True) for _ in range(copy_streams)]
+    ddst = [torch.empty(part, dtype=torch.uint8, device=dev) for _ in range(copy_streams)]
+    bulk = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(copy_streams):
+            with torch.cuda.stream(streams[j]):
+                ddst[j].copy_(hsrc[j], non_blocking=True)
+        torch.cuda.synchronize()
+        bulk = min(bulk, time.perf_counter() - t0)
+    return {"per_frame_copies_gbs": nbytes / best / 1e9, "bulk_copies_gbs": copy_streams * part / bulk / 1e9,
+            "demand_gbs": nbytes * fps / 1e9, "bytes_per_frame_set": nbytes, "pixel_updates_per_frame_set": npu,
+            "streams": len(plan),
+            "copy_streams": copy_streams,
+            "note": "best of 3 rounds; per-frame: one async copy per frame of every stream from the pinned "
+                    "pools, issued from Python; bulk: the same bytes in one copy per copy stream"}
 
 
 def bench_serve(args) -> int:
@@ -573,7 +591,8 @@ def bench_serve(args) -> int:
             (st.rgb(t).contiguous().pin_memory() if rgb else None,
              st.depth(t).contiguous().pin_memory() if dep else None) for t in range(8)]
     h2d = h2d_ceiling(pools, SERVE_MIX, args.serve_streams)
-    print(f"[serve] host->device: {h2d['ceiling_gbs']:.1f} GB/s over four copy streams, demand at 30 fps "
+    print(f"[serve] host->device: {h2d['bulk_copies_gbs']:.1f} GB/s in large copies, "
+          f"{h2d['per_frame_copies_gbs']:.1f} GB/s frame by frame; demand at 30 fps "
           f"{h2d['demand_gbs']:.1f} GB/s", file=sys.stderr, flush=True)
     budget = int(args.serve_budget_gb * (1 << 30))
     ex = NativeExecutor(ring=4, state_dtype=dtype, tuning=(256, 1024, 4), arena_bytes=budget)
@@ -585,6 +604,9 @@ def bench_serve(args) -> int:
     finally:
         srv.close()
         ex.close()
+    # host->device bytes the served frames moved per second over the measured window
+    pu_per_byte = h2d["pixel_updates_per_frame_set"] / h2d["bytes_per_frame_set"]
+    h2d["served_gbs"] = rep["pixel_updates_per_s"] / pu_per_byte / 1e9
     out = {
         "metric": "RGBD GMM pixel-updates/s", "value": rep["pixel_updates_per_s"], "unit": "pixel-updates/s",
         "n_gpus": 1, "steps": rep["frames_completed"], "warmup": 0, "ms_per_step": None,
