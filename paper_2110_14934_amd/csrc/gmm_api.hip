@@ -486,15 +486,13 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
     const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, static_cast<uint32_t>(h->esize)).bytes;
-    // tiled device layout -> canonical [param][rank][pixel]
-    const uint32_t nv = static_cast<uint32_t>(P * M);
+    // two-plane device layout -> canonical [param][rank][pixel]
     for (size_t k = 0; k < P * M; ++k) {
       const uint32_t v = value_index(static_cast<uint32_t>(k / M), static_cast<uint32_t>(k % M),
                                      static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
       for (size_t i = 0; i < n; ++i) {
-        const size_t at = off + (i / kWave) * tile_bytes +
-                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), static_cast<uint32_t>(M), C,
-                                            static_cast<uint32_t>(h->esize));
+        const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C,
+                                                   static_cast<uint32_t>(h->esize));
         unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
       }
       o += n;
@@ -528,15 +526,13 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
     const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, static_cast<uint32_t>(h->esize)).bytes;
-    // canonical [param][rank][pixel] -> tiled device layout
-    const uint32_t nv = static_cast<uint32_t>(P * M);
+    // canonical [param][rank][pixel] -> two-plane device layout
     for (size_t k = 0; k < P * M; ++k) {
       const uint32_t v = value_index(static_cast<uint32_t>(k / M), static_cast<uint32_t>(k % M),
                                      static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
       for (size_t i = 0; i < n; ++i) {
-        const size_t at = off + (i / kWave) * tile_bytes +
-                          tile_value_offset(v, static_cast<uint32_t>(i % kWave), static_cast<uint32_t>(M), C,
-                                            static_cast<uint32_t>(h->esize));
+        const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C,
+                                                   static_cast<uint32_t>(h->esize));
         pack_values(in + i, raw.data() + at, 1, h->cfg.state_dtype);
       }
       in += n;

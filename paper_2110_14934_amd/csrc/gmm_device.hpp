@@ -1,9 +1,9 @@
 // Device-side building blocks of the per-pixel mixture step (gfx950, wave64).
 //
-// One lane owns one pixel of one modality. Its M components are loaded from the tiled state
-// layout (below: per tile of 64 pixels, rows of 16-byte chunks shared by the wave's lanes, then
-// each lane's remaining values contiguous), advanced one frame in fp32 registers, re-sorted in
-// registers and written back.
+// One lane owns one pixel of one modality. Its M components are loaded from the two-plane state
+// layout (below: rows of 16-byte chunks shared by the 64 lanes of a tile, tile after tile, then
+// each pixel's remaining values contiguous in a second plane), advanced one frame in fp32
+// registers, re-sorted in registers and written back.
 // Every kernel of the library (plain, fused, batched) calls the same functions below, so all
 // of them produce bit-identical results for the same pixel.
 #pragma once
@@ -112,21 +112,24 @@ constexpr int kFastLoad = static_cast<int>(fast_load_count(M, C));
 template <int M, int C>
 constexpr int kFastStore = static_cast<int>(fast_store_count(M, C));
 
-// One modality's state block as a buffer resource, in a tiled layout. Pixels are grouped in
-// tiles of 64 (one wave); each pixel has NV = (C+2)*M values (in value_index order). A tile
-// holds two parts:
-//   rows   - the first npc 16-byte chunks of every lane: row c holds values [c*vpc, (c+1)*vpc)
-//            of lanes 0..63 as [lane][16 B] (vpc = 16 / sizeof(value)), so one wave instruction
-//            moves 1 KB of contiguous memory. npc covers the values a steady-state frame reads
-//            (the fast-path prefix) whenever NV leaves room for them in whole chunks;
-//   suffix - the remaining values of each lane, contiguous per lane and padded to whole 32-bit
-//            words: lane L's at npc KB + L*sb. A pixel that leaves the fast path reads and
-//            writes its suffix as a few contiguous bytes, not as 16-byte pieces of rows shared
-//            with 63 other pixels (whole sectors of which the memory would move).
-// A lane's tile + lane byte offset lives in one VGPR and every other offset is a compile-time
-// constant, so each state access is one buffer instruction. The range checked by the hardware
-// (num_records) is the whole block: an access outside it reads 0 and drops its write instead of
-// touching other memory. The host keeps every block below 4 GiB.
+// One modality's state block as a buffer resource, in two planes. Pixels are grouped in tiles
+// of 64 (one wave); each pixel has NV = (C+2)*M values (in value_index order).
+//   hot plane  - the first npc 16-byte chunks of every lane, tile after tile: row c of tile t
+//                holds values [c*vpc, (c+1)*vpc) of the tile's lanes 0..63 as [lane][16 B]
+//                (vpc = 16 / sizeof(value)), so one wave instruction moves 1 KB of contiguous
+//                memory and the rows of consecutive tiles are contiguous too. npc covers the
+//                values a steady-state frame reads (the fast-path prefix) whenever NV leaves room
+//                for them in whole chunks;
+//   cold plane - after the hot plane of all tiles: the remaining values of each pixel,
+//                contiguous per pixel and padded to whole 32-bit words (sb bytes), pixel p's at
+//                cold + p*sb. A pixel that leaves the fast path reads and writes its suffix as a
+//                few contiguous bytes.
+// A frame whose pixels keep to the fast path therefore streams through one dense plane and
+// skips the other, instead of reading part of every tile and stepping over the rest. A lane's
+// offsets are a VGPR plus compile-time constants, so each state access is one buffer
+// instruction. The range checked by the hardware (num_records) is the whole block: an access
+// outside it reads 0 and drops its write instead of touching other memory. The host keeps every
+// block below 4 GiB.
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
 constexpr uint32_t kChunkBytes = 16;
 constexpr uint32_t kRowBytes = 64u * kChunkBytes;
@@ -148,22 +151,24 @@ __host__ __device__ constexpr TileLayout tile_layout(uint32_t M, uint32_t C, uin
   return TileLayout{vpc, npc, rest, sb, npc * kRowBytes + 64u * sb};
 }
 
-// Byte offset, inside its tile, of value v of lane `lane`.
-__host__ __device__ constexpr uint32_t tile_value_offset(uint32_t v, uint32_t lane, uint32_t M, uint32_t C,
-                                                         uint32_t es) {
+// Byte offset, inside a block of `tiles64` tiles, of value v of pixel p.
+__host__ __device__ constexpr uint64_t state_value_offset(uint32_t v, uint64_t p, uint64_t tiles64, uint32_t M,
+                                                          uint32_t C, uint32_t es) {
   const TileLayout L = tile_layout(M, C, es);
-  return v < L.npc * L.vpc ? (v / L.vpc) * kRowBytes + lane * kChunkBytes + (v % L.vpc) * es
-                           : L.npc * kRowBytes + lane * L.sb + (v - L.npc * L.vpc) * es;
+  return v < L.npc * L.vpc
+             ? (p / 64u) * L.npc * kRowBytes + (v / L.vpc) * kRowBytes + (p % 64u) * kChunkBytes + (v % L.vpc) * es
+             : tiles64 * L.npc * kRowBytes + p * L.sb + (v - L.npc * L.vpc) * es;
 }
 
 struct StateBlock {
   __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t tile_bytes;
+  uint32_t tile_rows;  // hot bytes per tile: npc rows of 1 KB
+  uint32_t cold;       // byte offset of the cold plane
 };
 
-__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, uint32_t tile_bytes) {
-  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(tile_bytes * tiles64), kRsrcWord3),
-                    tile_bytes};
+__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, const TileLayout& L) {
+  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(L.bytes * tiles64), kRsrcWord3),
+                    L.npc * kRowBytes, tiles64 * L.npc * kRowBytes};
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -248,7 +253,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
   constexpr TileLayout L = tile_layout(M, C, es);
   constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
   const uint32_t lane = p & 63u;
-  const uint32_t base = (p >> 6) * b.tile_bytes;
+  const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, NV>([&](auto v_) RGBD_BODY {
     constexpr int v = RGBD_I(v_);
     if constexpr (!value_read<M, C, LIMIT, S>(v)) field<M, C, v>(m) = (v >= M && (v - M) % (C + 1) == 0) ? 1.f : 0.f;
@@ -264,7 +269,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
     }
   });
   if constexpr (LIMIT > nf && nw > 0) {
-    const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
+    const uint32_t sbase = b.cold + p * L.sb;
     // whole 16-byte groups of the suffix, then single words
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
@@ -296,7 +301,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
   constexpr TileLayout L = tile_layout(M, C, es);
   constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
   const uint32_t lane = p & 63u;
-  const uint32_t base = (p >> 6) * b.tile_bytes;
+  const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, npc>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
     if constexpr (c * vpc >= LF) {
@@ -308,7 +313,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
     }
   });
   if constexpr (LF <= nf && nw > 0) {
-    const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
+    const uint32_t sbase = b.cold + p * L.sb;
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
       const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, sbase + 16u * g, 0, 0);
@@ -339,7 +344,7 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
   constexpr TileLayout L = tile_layout(M, C, es);
   constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
   const uint32_t lane = p & 63u;
-  const uint32_t base = (p >> 6) * b.tile_bytes;
+  const uint32_t base = (p >> 6) * b.tile_rows;
   // suffix value v, or 0 for a padding half
   auto sv = [&](auto v_) RGBD_BODY -> float {
     constexpr int v = RGBD_I(v_);
@@ -358,7 +363,7 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
     }
   });
   if constexpr (SUFFIX && LIMIT > nf && nw > 0) {
-    const uint32_t sbase = base + npc * kRowBytes + lane * L.sb;
+    const uint32_t sbase = b.cold + p * L.sb;
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
       u32x4 w = {0u, 0u, 0u, 0u};
@@ -386,7 +391,7 @@ __device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateB
   constexpr TileLayout L = tile_layout(M, C, es);
   constexpr int vpc = L.vpc, npc = L.npc;
   const uint32_t lane = p & 63u;
-  const uint32_t base = (p >> 6) * b.tile_bytes;
+  const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, npc>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
     if constexpr (c * vpc >= FROM) {
@@ -428,9 +433,8 @@ template <int M, int C, typename S>
 __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool all, int r) {
   constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
   constexpr TileLayout L = tile_layout(M, C, es);
-  constexpr int npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
-  const uint32_t lane = p & 63u;
-  const uint32_t sbase = (p >> 6) * b.tile_bytes + npc * kRowBytes + lane * L.sb;
+  constexpr int nf = L.npc * L.vpc, nw = L.sb / 4;
+  const uint32_t sbase = b.cold + p * L.sb;
   const int lo = M + r * (C + 1), hi = lo + C + 1;
   auto sv = [&](auto v_) RGBD_BODY -> float {
     constexpr int v = RGBD_I(v_);

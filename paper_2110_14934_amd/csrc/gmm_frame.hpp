@@ -149,7 +149,7 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   bool fgc = false, fgd = false;
   uint32_t wave_bytes = 0;
   if (AUG && (mode & kModeAug) != 0) {
-    const StateBlock blk = make_block(a.st_rgb, a.tiles64, tile_layout(M, 4, sizeof(S)).bytes);
+    const StateBlock blk = make_block(a.st_rgb, a.tiles64, tile_layout(M, 4, sizeof(S)));
     Mix<M, 4> m;
     load_prefix<M, 4, S>(m, blk, p, valid);
     const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
@@ -162,8 +162,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
   const bool do_c = (mode & kModeRGB) != 0, do_d = (mode & kModeDepth) != 0, do_f = (mode & kModeFuse) != 0;
-  const StateBlock blk_c = make_block(a.st_rgb, a.tiles64, tile_layout(M, 3, sizeof(S)).bytes);
-  const StateBlock blk_d = make_block(a.st_depth, a.tiles64, tile_layout(M, 1, sizeof(S)).bytes);
+  const StateBlock blk_c = make_block(a.st_rgb, a.tiles64, tile_layout(M, 3, sizeof(S)));
+  const StateBlock blk_d = make_block(a.st_depth, a.tiles64, tile_layout(M, 1, sizeof(S)));
   Mix<M, 3> mc;
   Mix<M, 1> md;
   // Every load of the pixel is issued before any result is used (the state blocks, the fusion

@@ -23,8 +23,8 @@ struct FrameArgs {
   int64_t rgb_pitch;
   const uint16_t* depth;
   int64_t depth_pitch;
-  void* st_rgb;            // colour state block: 5*M values per pixel, tiled (four-channel variant: 6*M)
-  void* st_depth;          // depth state block: 3*M values per pixel, tiled
+  void* st_rgb;            // colour state block: 5*M values per pixel, two planes (four-channel variant: 6*M)
+  void* st_depth;          // depth state block: 3*M values per pixel, two planes
   uint8_t* fstate;         // List 1 state bytes
   uint64_t* fg_rgb;
   uint64_t* fg_depth;

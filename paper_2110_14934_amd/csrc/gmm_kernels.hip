@@ -4,9 +4,10 @@
 // its foreground bits form exactly one uint64 word of the output mask (one ballot, one store).
 // The interleaved RGB8 input of a wave (192 contiguous bytes when rows are dense) is staged
 // through LDS with 48 dword loads and de-interleaved on chip - the structure-of-arrays split of
-// the colour image done without a separate pass. The state is tiled per wave: a chunk-row load
-// or store of a wave moves 1 KB of contiguous memory, and a pixel's remaining values are
-// contiguous.
+// the colour image done without a separate pass. The state is kept in two planes per modality:
+// chunk rows of the fast-path values (a wave's row load or store moves 1 KB of contiguous memory,
+// and the rows of consecutive waves follow each other), then each pixel's remaining values,
+// contiguous per pixel.
 #include <hip/hip_runtime.h>
 
 #include "gmm_device.hpp"
@@ -46,8 +47,8 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
   if (lane == 0 && valid) out[word] = bits;
 }
 
-// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks), tiled layout.
-// (Padding halves of 16-bit suffix words are never read.)
+// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks), two-plane
+// layout. (Padding halves of 16-bit suffix words are never read.)
 template <typename S>
 __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, int M, int C, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -57,8 +58,8 @@ __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, i
   const uint32_t lane = static_cast<uint32_t>(i % kWave);
   const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
   const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
-  const uint32_t tb = tile_layout(static_cast<uint32_t>(M), static_cast<uint32_t>(C), sizeof(S)).bytes;
-  const int64_t byte = tile * tb + tile_value_offset(v, lane, static_cast<uint32_t>(M), static_cast<uint32_t>(C), sizeof(S));
+  const uint64_t byte = state_value_offset(v, static_cast<uint64_t>(tile) * kWave + lane, tiles64,
+                                           static_cast<uint32_t>(M), static_cast<uint32_t>(C), sizeof(S));
   // value order: M weights, then per rank (variance, C means)
   const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
   *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(is_var ? var0 : 0.f);

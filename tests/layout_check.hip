@@ -1,7 +1,9 @@
-// Host-side check of the tiled state layout (no GPU needed): for every compiled (M, C, value
-// size), every value of every lane of a tile has its own aligned bytes inside the tile, the
-// fast-path prefix lies in the chunk rows whenever whole chunks can hold it, the suffix of each
-// lane is contiguous, and the fast path's stores cover only values its loads read.
+// Host-side check of the two-plane state layout (no GPU needed): for every compiled (M, C,
+// value size) and a block of a few tiles, every value of every pixel has its own aligned bytes
+// inside the block, the chunk rows of all tiles come first (row c of tile t at t*npc KB + c KB),
+// the suffix of each pixel is contiguous at cold + p*sb, the fast-path prefix lies in the chunk
+// rows whenever whole chunks can hold it, and the fast path's stores cover only values its loads
+// read.
 #include <cstdio>
 #include <vector>
 
@@ -13,24 +15,31 @@ template <int M, int C, typename S>
 static int check() {
   constexpr uint32_t es = sizeof(S), nv = (C + 2) * M;
   constexpr TileLayout L = tile_layout(M, C, es);
+  constexpr uint64_t tiles = 3;
+  const uint64_t block = tiles * L.bytes, cold = tiles * L.npc * kRowBytes;
   int bad = 0;
-  std::vector<int> owner(L.bytes, -1);
-  for (uint32_t lane = 0; lane < 64; ++lane)
+  std::vector<int64_t> owner(block, -1);
+  for (uint64_t p = 0; p < tiles * 64; ++p)
     for (uint32_t v = 0; v < nv; ++v) {
-      const uint32_t off = tile_value_offset(v, lane, M, C, es);
-      if (off % es || off + es > L.bytes) {
-        std::printf("M=%d C=%d es=%u: value %u lane %u at %u out of tile (%u bytes)\n", M, C, es, v, lane, off, L.bytes);
+      const uint64_t off = state_value_offset(v, p, tiles, M, C, es);
+      if (off % es || off + es > block) {
+        std::printf("M=%d C=%d es=%u: value %u pixel %llu at %llu out of the block (%llu bytes)\n", M, C, es, v,
+                    (unsigned long long)p, (unsigned long long)off, (unsigned long long)block);
         ++bad;
         continue;
       }
       for (uint32_t b = 0; b < es; ++b) {
         if (owner[off + b] != -1) {
-          std::printf("M=%d C=%d es=%u: byte %u shared\n", M, C, es, off + b);
+          std::printf("M=%d C=%d es=%u: byte %llu shared\n", M, C, es, (unsigned long long)(off + b));
           ++bad;
         }
-        owner[off + b] = static_cast<int>(lane * nv + v);
+        owner[off + b] = static_cast<int64_t>(p * nv + v);
       }
-      if (v >= L.npc * L.vpc && off != L.npc * kRowBytes + lane * L.sb + (v - L.npc * L.vpc) * es) ++bad;
+      const uint32_t nf = L.npc * L.vpc;
+      if (v >= nf && off != cold + p * L.sb + (v - nf) * es) ++bad;
+      if (v < nf && off != (p / 64) * L.npc * kRowBytes + (v / L.vpc) * kRowBytes + (p % 64) * kChunkBytes +
+                               (v % L.vpc) * es)
+        ++bad;
     }
   if (L.sb % 4 || L.npc * kRowBytes + 64 * L.sb != L.bytes || L.rest * es > L.sb) ++bad;
   const uint32_t lf = fast_load_count(M, C);

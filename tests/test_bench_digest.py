@@ -30,10 +30,25 @@ def test_comments_do_not_change_the_digest_code_does(tmp_path, monkeypatch):
     assert _digest_of(tmp_path / "d", monkeypatch, flags) != d0
 
 
-def test_recorded_traffic_matches_the_current_kernel():
+def test_recorded_traffic_is_reported_only_for_the_kernel_it_was_measured_on(tmp_path, monkeypatch):
     import json
-    rec = json.load(open(os.path.join(bench.ROOT, "profiles", "traffic_frame_kernel_plain-640x480.json")))
-    assert rec["kernel_source_digest"] == bench.kernel_source_digest("frame")
+    for wl, kind in (("plain-640x480", "frame"), ("batch-64", "batch")):
+        path = bench.PROFILE_TRAFFIC[wl]
+        assert os.path.exists(path), path
+        rec = json.load(open(path))
+        assert rec["hbm_bytes_per_launch"] > 0 and rec["kernel_source_digest"]
+        traffic, _ = bench._traffic(wl, kind)
+        assert traffic == (rec["hbm_bytes_per_launch"] if rec["kernel_source_digest"] == bench.kernel_source_digest(kind)
+                           else None)
+        # a record whose digest is the current kernel's is reported
+        fake = dict(rec, kernel_source_digest=bench.kernel_source_digest(kind))
+        p = tmp_path / f"{wl}.json"
+        p.write_text(json.dumps(fake))
+        monkeypatch.setitem(bench.PROFILE_TRAFFIC, wl, str(p))
+        assert bench._traffic(wl, kind)[0] == rec["hbm_bytes_per_launch"]
+        fake["kernel_source_digest"] = "0" * 16
+        p.write_text(json.dumps(fake))
+        assert bench._traffic(wl, kind)[0] is None
 
 
 def test_clip_plays_forwards_then_backwards_without_a_jump():
