@@ -21,7 +21,7 @@ namespace rgbd {
 // compiler may turn "a ? v[r-1] : v[r]" into a load from a selected address before the loop is
 // unrolled; the array then needs memory and lands in LDS, one round trip per access.)
 template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
+__host__ __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (B < E) {
     f(std::integral_constant<int, B>{});
     static_for<B + 1, E>(f);
@@ -114,71 +114,162 @@ constexpr int kFastStore = static_cast<int>(fast_store_count(M, C));
 
 // One modality's state block as a buffer resource, in two planes. Pixels are grouped in tiles
 // of 64 (one wave); each pixel has NV = (C+2)*M values (in value_index order).
-//   hot plane  - the first npc 16-byte chunks of every lane, tile after tile: row c of tile t
-//                holds values [c*vpc, (c+1)*vpc) of the tile's lanes 0..63 as [lane][16 B]
-//                (vpc = 16 / sizeof(value)), so one wave instruction moves 1 KB of contiguous
-//                memory and the rows of consecutive tiles are contiguous too. npc covers the
-//                values a steady-state frame reads (the fast-path prefix) whenever NV leaves room
-//                for them in whole chunks;
+//   hot plane  - rows holding the values a steady-state frame touches, tile after tile. Row c
+//                holds values [first[c], first[c+1]) of the tile's 64 lanes as [lane][width[c]]
+//                with width[c] = 16, 8 or 4 bytes, so one wave instruction moves 1 KB, 512 B or
+//                256 B of contiguous memory, and the rows of consecutive tiles are contiguous
+//                too. The rows end exactly where the fast path's stores end and where its loads
+//                end (whole 32-bit words), so a frame on the fast path moves no value it does not
+//                need;
 //   cold plane - after the hot plane of all tiles: the remaining values of each pixel,
 //                contiguous per pixel and padded to whole 32-bit words (sb bytes), pixel p's at
 //                cold + p*sb. A pixel that leaves the fast path reads and writes its suffix as a
 //                few contiguous bytes.
 // A frame whose pixels keep to the fast path therefore streams through one dense plane and
-// skips the other, instead of reading part of every tile and stepping over the rest. A lane's
-// offsets are a VGPR plus compile-time constants, so each state access is one buffer
-// instruction. The range checked by the hardware (num_records) is the whole block: an access
-// outside it reads 0 and drops its write instead of touching other memory. The host keeps every
-// block below 4 GiB.
+// skips the other. A lane's offsets are a VGPR plus compile-time constants, so each state access
+// is one buffer instruction. The range checked by the hardware (num_records) is the whole block:
+// an access outside it reads 0 and drops its write instead of touching other memory. The host
+// keeps every block below 4 GiB.
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
-constexpr uint32_t kChunkBytes = 16;
-constexpr uint32_t kRowBytes = 64u * kChunkBytes;
+constexpr uint32_t kMaxRows = 8;
 
 struct TileLayout {
-  uint32_t vpc;    // values per 16-byte chunk
-  uint32_t npc;    // chunk rows
-  uint32_t rest;   // values per lane in the suffix
-  uint32_t sb;     // suffix bytes per lane (whole words)
-  uint32_t bytes;  // bytes per tile
+  uint32_t nrows = 0;                // hot rows
+  uint32_t width[kMaxRows] = {};     // bytes per lane of each row: 16, 8 or 4
+  uint32_t first[kMaxRows + 1] = {};  // first value of each row; first[nrows] = nf
+  uint32_t off[kMaxRows + 1] = {};    // byte offset of each row inside the tile's hot bytes
+  uint32_t hot = 0;                  // hot bytes per lane (sum of the widths)
+  uint32_t nf = 0;                   // values held by the hot rows
+  uint32_t rest = 0;                 // values per pixel in the cold plane
+  uint32_t sb = 0;                   // cold bytes per pixel (whole 32-bit words)
+  uint32_t bytes = 0;                // bytes per tile of 64 pixels: 64 * (hot + sb)
 };
 
+// Rows covering values [0, fast_store_count) and then [fast_store_count, fast_load_count), each
+// range rounded up to whole 32-bit words and cut greedily into 16-, 8- and 4-byte rows (a 16-bit
+// value left alone shares its word with the next value, or with padding past the last one).
 __host__ __device__ constexpr TileLayout tile_layout(uint32_t M, uint32_t C, uint32_t es) {
-  const uint32_t nv = (C + 2) * M, vpc = kChunkBytes / es;
-  const uint32_t want = (fast_load_count(M, C) + vpc - 1) / vpc, whole = nv / vpc;
-  const uint32_t npc = want < whole ? want : whole;
-  const uint32_t rest = nv - npc * vpc;
-  const uint32_t sb = (rest * es + 3u) / 4u * 4u;
-  return TileLayout{vpc, npc, rest, sb, npc * kRowBytes + 64u * sb};
+  TileLayout L{};
+  const uint32_t nv = (C + 2) * M;
+  const uint32_t ends[2] = {fast_store_count(M, C), fast_load_count(M, C)};
+  uint32_t v = 0;
+  for (uint32_t seg = 0; seg < 2; ++seg) {
+    const uint32_t end = ends[seg] < nv ? ends[seg] : nv;
+    while (v < end && L.nrows < kMaxRows) {
+      const uint32_t left = ((end - v) * es + 3u) / 4u * 4u;  // whole 32-bit words
+      const uint32_t w = left >= 16 ? 16u : (left >= 8 ? 8u : 4u);
+      L.width[L.nrows] = w;
+      L.first[L.nrows] = v;
+      L.off[L.nrows] = 64u * L.hot;
+      L.hot += w;
+      ++L.nrows;
+      v += w / es;
+    }
+  }
+  L.nf = v < nv ? v : nv;
+  L.first[L.nrows] = L.nf;
+  L.off[L.nrows] = 64u * L.hot;
+  L.rest = nv - L.nf;
+  L.sb = (L.rest * es + 3u) / 4u * 4u;
+  L.bytes = 64u * (L.hot + L.sb);
+  return L;
 }
+
+// The layout of one (M, C, storage type), as a constant every kernel can index at compile time.
+template <int M, int C, typename S>
+struct Plan {
+  static constexpr TileLayout L = tile_layout(M, C, sizeof(S));
+  // the scalars device code uses, so that no layout object is ever built at run time
+  static constexpr uint32_t nrows = L.nrows, hot = L.hot, nf = L.nf, sb = L.sb, bytes = L.bytes;
+};
 
 // Byte offset, inside a block of `tiles64` tiles, of value v of pixel p.
 __host__ __device__ constexpr uint64_t state_value_offset(uint32_t v, uint64_t p, uint64_t tiles64, uint32_t M,
                                                           uint32_t C, uint32_t es) {
   const TileLayout L = tile_layout(M, C, es);
-  return v < L.npc * L.vpc
-             ? (p / 64u) * L.npc * kRowBytes + (v / L.vpc) * kRowBytes + (p % 64u) * kChunkBytes + (v % L.vpc) * es
-             : tiles64 * L.npc * kRowBytes + p * L.sb + (v - L.npc * L.vpc) * es;
+  if (v >= L.nf) return tiles64 * 64u * L.hot + p * L.sb + (v - L.nf) * es;
+  uint32_t c = 0;
+  while (L.first[c + 1] <= v) ++c;
+  return (p / 64u) * 64u * L.hot + L.off[c] + (p % 64u) * L.width[c] + (v - L.first[c]) * es;
+}
+
+// The same offset in device code, for a layout known at compile time (the row is found by
+// comparisons with constants, so no layout table is built at run time).
+template <int M, int C, typename S>
+__host__ __device__ __forceinline__ uint64_t value_offset(uint32_t v, uint64_t p, uint64_t tiles64) {
+  using P = Plan<M, C, S>;
+  constexpr uint32_t es = sizeof(S);
+  uint64_t off = tiles64 * 64u * P::hot + p * P::sb + static_cast<uint64_t>(v - P::nf) * es;
+  static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    constexpr uint32_t a = P::L.first[c], e = P::L.first[c + 1], W = P::L.width[c], o = P::L.off[c];
+    if (v >= a && v < e) off = (p / 64u) * 64u * P::hot + o + (p % 64u) * W + (v - a) * es;
+  });
+  return off;
 }
 
 struct StateBlock {
   __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t tile_rows;  // hot bytes per tile: npc rows of 1 KB
+  uint32_t tile_rows;  // hot bytes per tile: 64 * hot
   uint32_t cold;       // byte offset of the cold plane
 };
 
-__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64, const TileLayout& L) {
-  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(L.bytes * tiles64), kRsrcWord3),
-                    L.npc * kRowBytes, tiles64 * L.npc * kRowBytes};
+template <int M, int C, typename S>
+__device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64) {
+  using P = Plan<M, C, S>;
+  return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(P::bytes * tiles64), kRsrcWord3),
+                    64u * P::hot, tiles64 * 64u * P::hot};
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// One lane's words of a row (W bytes), moved by one buffer instruction of that width.
+template <uint32_t W>
+struct RowWords {
+  uint32_t w[W / 4];
+};
+
+template <uint32_t W>
+__device__ __forceinline__ RowWords<W> load_row(const __amdgpu_buffer_rsrc_t& r, uint32_t off) {
+  RowWords<W> o{};
+  if constexpr (W == 16) {
+    const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    o.w[0] = x[0];
+    o.w[1] = x[1];
+    o.w[2] = x[2];
+    o.w[3] = x[3];
+  } else if constexpr (W == 8) {
+    const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    o.w[0] = x[0];
+    o.w[1] = x[1];
+  } else {
+    static_assert(W == 4, "rows are 16, 8 or 4 bytes per lane");
+    o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  }
+  return o;
+}
+
+template <uint32_t W>
+__device__ __forceinline__ void store_row(const RowWords<W>& o, const __amdgpu_buffer_rsrc_t& r, uint32_t off) {
+  if constexpr (W == 16) {
+    const u32x4 x = {o.w[0], o.w[1], o.w[2], o.w[3]};
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, 0);
+  } else if constexpr (W == 8) {
+    const u32x2 x = {o.w[0], o.w[1]};
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
+  } else {
+    static_assert(W == 4, "rows are 16, 8 or 4 bytes per lane");
+    __builtin_amdgcn_raw_buffer_store_b32(o.w[0], r, off, 0, 0);
+  }
+}
 
 template <typename S> struct BufIO;
 template <> struct BufIO<float> {
   // the 32-bit word holding value a (and b, for 16-bit types, in the high half); by value, so
   // the values stay in registers
   static __device__ __forceinline__ uint32_t word(float a, float) { return __builtin_bit_cast(uint32_t, a); }
-  // value `half` of a word (the lower-addressed one first); the b32/b128 builtins move raw
+  // value `half` of a word (the lower-addressed one first); the buffer builtins move raw
   // words: reinterpret, never convert
   static __device__ __forceinline__ float from_word(uint32_t w, int) { return __builtin_bit_cast(float, w); }
 };
@@ -199,14 +290,16 @@ template <> struct BufIO<bf16s> {
   }
 };
 
-// Whether a load of values [0, LIMIT) reads value v: a chunk row comes whole when it starts
-// below LIMIT (so it may carry values at or beyond LIMIT), and the suffix comes whole when
-// LIMIT reaches into it.
+// Whether a load of values [0, LIMIT) reads value v: a row comes whole when it starts below
+// LIMIT (so it may carry values at or beyond LIMIT), and the suffix comes whole when LIMIT
+// reaches into it.
 template <int M, int C, int LIMIT, typename S>
 __host__ __device__ constexpr bool value_read(uint32_t v) {
-  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
-  return v < L.npc * L.vpc ? (v / L.vpc) * L.vpc < static_cast<uint32_t>(LIMIT)
-                           : static_cast<uint32_t>(LIMIT) > L.npc * L.vpc;
+  using P = Plan<M, C, S>;
+  if (v >= P::nf) return static_cast<uint32_t>(LIMIT) > P::nf;
+  uint32_t c = 0;
+  while (P::L.first[c + 1] <= v) ++c;
+  return P::L.first[c] < static_cast<uint32_t>(LIMIT);
 }
 
 // Every value a store of [0, SF) writes is one a load of [0, LF) read.
@@ -221,11 +314,20 @@ __host__ __device__ constexpr bool stores_only_read() {
 // load_mix / store_mix move them.
 template <int M, int C, int LIMIT, typename S>
 __host__ __device__ constexpr uint32_t prefix_bytes() {
-  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
-  uint32_t rows = 0;
-  for (uint32_t c = 0; c < L.npc; ++c)
-    if (c * L.vpc < static_cast<uint32_t>(LIMIT)) ++rows;
-  return rows * kRowBytes + (static_cast<uint32_t>(LIMIT) > L.npc * L.vpc ? 64u * L.sb : 0u);
+  using P = Plan<M, C, S>;
+  uint32_t b = 0;
+  for (uint32_t c = 0; c < P::nrows; ++c)
+    if (P::L.first[c] < static_cast<uint32_t>(LIMIT)) b += 64u * P::L.width[c];
+  return b + (static_cast<uint32_t>(LIMIT) > P::nf ? 64u * P::sb : 0u);
+}
+
+// Whether some row starts at or after value FROM (rows a store of [0, FROM) leaves out).
+template <int M, int C, int FROM, typename S>
+__host__ __device__ constexpr bool rows_from_exist() {
+  using P = Plan<M, C, S>;
+  for (uint32_t c = 0; c < P::nrows; ++c)
+    if (P::L.first[c] >= static_cast<uint32_t>(FROM)) return true;
+  return false;
 }
 
 // Value V (in value_index order) of a pixel's mixture, as the Mix field that holds it.
@@ -244,32 +346,60 @@ __device__ __forceinline__ float field(const Mix<M, C>& m) {
   return field<M, C, V>(const_cast<Mix<M, C>&>(m));
 }
 
+// Value V, or 0 past the last value (the padding half of a 16-bit word).
+template <int M, int C, int V>
+__device__ __forceinline__ float value_or_pad(const Mix<M, C>& m) {
+  if constexpr (V < (C + 2) * M) return field<M, C, V>(m);
+  else return 0.f;
+}
+
+// Row c of pixel p into the Mix (values past the last one are padding and dropped).
+template <int M, int C, typename S, int c>
+__device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane) {
+  constexpr int NV = (C + 2) * M, vpw = 4 / static_cast<int>(sizeof(S));
+  constexpr uint32_t W = Plan<M, C, S>::L.width[c], off = Plan<M, C, S>::L.off[c];
+  constexpr int v0 = static_cast<int>(Plan<M, C, S>::L.first[c]);
+  const RowWords<W> o = load_row<W>(b.rsrc, base + off + lane * W);
+  static_for<0, static_cast<int>(W / sizeof(S))>([&](auto i_) RGBD_BODY {
+    constexpr int i = RGBD_I(i_);
+    if constexpr (v0 + i < NV) field<M, C, v0 + i>(m) = BufIO<S>::from_word(o.w[i / vpw], i % vpw);
+  });
+}
+
+// Row c of pixel p from the Mix.
+template <int M, int C, typename S, int c>
+__device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane) {
+  constexpr int vpw = 4 / static_cast<int>(sizeof(S));
+  constexpr uint32_t W = Plan<M, C, S>::L.width[c], off = Plan<M, C, S>::L.off[c];
+  constexpr int v0 = static_cast<int>(Plan<M, C, S>::L.first[c]);
+  RowWords<W> o{};
+  static_for<0, static_cast<int>(W / 4)>([&](auto k_) RGBD_BODY {
+    constexpr int k = RGBD_I(k_);
+    o.w[k] = BufIO<S>::word(value_or_pad<M, C, v0 + k * vpw>(m), value_or_pad<M, C, v0 + k * vpw + vpw - 1>(m));
+  });
+  store_row<W>(o, b.rsrc, base + off + lane * W);
+}
+
 // Values [0, LIMIT) of pixel p, straight into the Mix (see value_read for what comes along). A
 // value not read is left at 0 - a variance at 1, so that keys stay finite (any use of it is
 // discarded by the caller). LIMIT = NV reads everything.
 template <int M, int C, typename S, int LIMIT = (C + 2) * M>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
   constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
-  constexpr TileLayout L = tile_layout(M, C, es);
-  constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
+  using P = Plan<M, C, S>;
+  constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, NV>([&](auto v_) RGBD_BODY {
     constexpr int v = RGBD_I(v_);
     if constexpr (!value_read<M, C, LIMIT, S>(v)) field<M, C, v>(m) = (v >= M && (v - M) % (C + 1) == 0) ? 1.f : 0.f;
   });
-  static_for<0, npc>([&](auto c_) RGBD_BODY {
+  static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (c * vpc < LIMIT) {
-      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
-      static_for<0, vpc>([&](auto i_) RGBD_BODY {
-        constexpr int i = RGBD_I(i_);
-        field<M, C, c * vpc + i>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
-      });
-    }
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) read_row<M, C, S, c>(m, b, base, lane);
   });
   if constexpr (LIMIT > nf && nw > 0) {
-    const uint32_t sbase = b.cold + p * L.sb;
+    const uint32_t sbase = b.cold + p * P::sb;
     // whole 16-byte groups of the suffix, then single words
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
@@ -292,28 +422,22 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
   }
 }
 
-// The values of pixel p that a load of [0, LF) did not bring: the chunk rows from the first one
+// The values of pixel p that a load of [0, LF) did not bring: the rows from the first one
 // starting at or past LF, and the suffix unless that load read it. With load_mix<LF> before it,
 // the Mix holds the whole state.
 template <int M, int C, typename S, int LF>
 __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
   constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
-  constexpr TileLayout L = tile_layout(M, C, es);
-  constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
+  using P = Plan<M, C, S>;
+  constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
-  static_for<0, npc>([&](auto c_) RGBD_BODY {
+  static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (c * vpc >= LF) {
-      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
-      static_for<0, vpc>([&](auto i_) RGBD_BODY {
-        constexpr int i = RGBD_I(i_);
-        field<M, C, c * vpc + i>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
-      });
-    }
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= LF) read_row<M, C, S, c>(m, b, base, lane);
   });
   if constexpr (LF <= nf && nw > 0) {
-    const uint32_t sbase = b.cold + p * L.sb;
+    const uint32_t sbase = b.cold + p * P::sb;
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
       const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, sbase + 16u * g, 0, 0);
@@ -335,73 +459,51 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
   }
 }
 
-// Values [0, LIMIT) of pixel p from the Mix (whole chunk rows and the whole suffix, as load_mix
-// reads them). ROWS / SUFFIX select the parts written, so that a caller can store the chunk rows
-// of every lane with one instruction per row and the suffix of some lanes only.
+// Values [0, LIMIT) of pixel p from the Mix (whole rows and the whole suffix, as load_mix reads
+// them). ROWS / SUFFIX select the parts written, so that a caller can store the rows of every
+// lane with one instruction per row and the suffix of some lanes only.
 template <int M, int C, typename S, int LIMIT = (C + 2) * M, bool ROWS = true, bool SUFFIX = true>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
-  constexpr TileLayout L = tile_layout(M, C, es);
-  constexpr int vpc = L.vpc, npc = L.npc, nf = L.npc * L.vpc, nw = L.sb / 4;
+  constexpr int es = sizeof(S), vpw = 4 / es;
+  using P = Plan<M, C, S>;
+  constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
-  // suffix value v, or 0 for a padding half
-  auto sv = [&](auto v_) RGBD_BODY -> float {
-    constexpr int v = RGBD_I(v_);
-    if constexpr (v < NV) return field<M, C, v>(m);
-    else return 0.f;
-  };
-  static_for<0, npc>([&](auto c_) RGBD_BODY {
+  static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (ROWS && c * vpc < LIMIT) {
-      u32x4 w = {0u, 0u, 0u, 0u};
-      static_for<0, 4>([&](auto i_) RGBD_BODY {
-        constexpr int i = RGBD_I(i_);
-        w[i] = BufIO<S>::word(field<M, C, c * vpc + i * vpw>(m), field<M, C, c * vpc + i * vpw + vpw - 1>(m));
-      });
-      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
-    }
+    if constexpr (ROWS && static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) write_row<M, C, S, c>(m, b, base, lane);
   });
   if constexpr (SUFFIX && LIMIT > nf && nw > 0) {
-    const uint32_t sbase = b.cold + p * L.sb;
+    const uint32_t sbase = b.cold + p * P::sb;
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
       u32x4 w = {0u, 0u, 0u, 0u};
       static_for<0, 4>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         constexpr int v = nf + (4 * g + i) * vpw;
-        w[i] = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+        w[i] = BufIO<S>::word(value_or_pad<M, C, v>(m), value_or_pad<M, C, v + vpw - 1>(m));
       });
       __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, sbase + 16u * g, 0, 0);
     });
     static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
       constexpr int wi = RGBD_I(w_);
       constexpr int v = nf + wi * vpw;
-      const uint32_t w = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+      const uint32_t w = BufIO<S>::word(value_or_pad<M, C, v>(m), value_or_pad<M, C, v + vpw - 1>(m));
       __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, sbase + 4u * wi, 0, 0);
     });
   }
 }
 
-// The chunk rows c with c * vpc >= FROM of pixel p from the Mix: the rows a row store of values
-// [0, FROM) leaves out.
+// The rows of pixel p starting at or after value FROM, from the Mix: the rows a row store of
+// values [0, FROM) leaves out.
 template <int M, int C, typename S, int FROM>
 __device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr int es = sizeof(S), vpw = 4 / es;
-  constexpr TileLayout L = tile_layout(M, C, es);
-  constexpr int vpc = L.vpc, npc = L.npc;
+  using P = Plan<M, C, S>;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
-  static_for<0, npc>([&](auto c_) RGBD_BODY {
+  static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (c * vpc >= FROM) {
-      u32x4 w = {0u, 0u, 0u, 0u};
-      static_for<0, 4>([&](auto i_) RGBD_BODY {
-        constexpr int i = RGBD_I(i_);
-        w[i] = BufIO<S>::word(field<M, C, c * vpc + i * vpw>(m), field<M, C, c * vpc + i * vpw + vpw - 1>(m));
-      });
-      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, base + lane * kChunkBytes + c * kRowBytes, 0, 0);
-    }
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= FROM) write_row<M, C, S, c>(m, b, base, lane);
   });
 }
 
@@ -416,8 +518,8 @@ __host__ __device__ constexpr bool holds_rank(int a, int e, int r) {
 template <int M, int C, typename S>
 __host__ __device__ constexpr uint32_t suffix_rank_bytes(int r) {
   constexpr int vpw = 4 / static_cast<int>(sizeof(S));
-  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
-  constexpr int nf = L.npc * L.vpc, nw = L.sb / 4;
+  using P = Plan<M, C, S>;
+  constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   uint32_t n = 0;
   for (int g = 0; g < nw / 4; ++g) n += holds_rank<M, C>(nf + 4 * g * vpw, nf + (4 * g + 4) * vpw, r) ? 16u : 0u;
   for (int wi = (nw / 4) * 4; wi < nw; ++wi) n += holds_rank<M, C>(nf + wi * vpw, nf + (wi + 1) * vpw, r) ? 4u : 0u;
@@ -426,15 +528,15 @@ __host__ __device__ constexpr uint32_t suffix_rank_bytes(int r) {
 
 // The suffix of pixel p from the Mix, piece by piece as store_mix cuts it (16-byte groups, then
 // words): every piece when `all`, else only the pieces holding a value of rank r. After a frame
-// in which the updated component kept its rank r, only the weights (in the chunk rows) and rank
+// in which the updated component kept its rank r, only the weights (in the hot rows) and rank
 // r changed: any other piece would rewrite the bits it holds, and each piece is one more write
 // request of a lane.
 template <int M, int C, typename S>
 __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool all, int r) {
   constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
-  constexpr TileLayout L = tile_layout(M, C, es);
-  constexpr int nf = L.npc * L.vpc, nw = L.sb / 4;
-  const uint32_t sbase = b.cold + p * L.sb;
+  using P = Plan<M, C, S>;
+  constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
+  const uint32_t sbase = b.cold + p * P::sb;
   const int lo = M + r * (C + 1), hi = lo + C + 1;
   auto sv = [&](auto v_) RGBD_BODY -> float {
     constexpr int v = RGBD_I(v_);

@@ -96,8 +96,8 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   constexpr int LF = kFastLoad<M, C>;
   constexpr int SF = kFastStore<M, C>;
   static_assert(stores_only_read<M, C, LF, SF, S>(), "the fast path writes back a value it did not read");
-  constexpr TileLayout L = tile_layout(M, C, sizeof(S));
-  constexpr int NR = static_cast<int>(L.npc * L.vpc);  // values held by the chunk rows
+  using P = Plan<M, C, S>;
+  constexpr int NR = static_cast<int>(P::nf);  // values held by the hot rows
   bool fg = false;
   const Mix<M, C> read = m;  // the prefix as read (fast_step updates m in place)
   const bool slow = active && !fast_step<M, C>(m, x, k);
@@ -110,15 +110,15 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
     kept = (j < M ? j : M - 1) == q ? q : -1;
   }
   // Write-back: every piece both paths write goes out in one store for all the lanes that write
-  // it (a 1 KB chunk row then leaves the wave as one write, not as one per path). Both paths
-  // write the chunk rows the fast prefix covers; when the fast store reaches into the suffix
-  // (the rows cannot hold the prefix), both write the suffix too. Rows past the prefix, and
+  // it (a hot row then leaves the wave as one write, not as one per path). Both paths write the
+  // rows the fast store covers; when the fast store reaches into the suffix (the rows cannot
+  // hold the prefix), both write the suffix too. Rows past the fast store, and
   // otherwise the suffix, are the general path's alone; of the suffix, a lane whose updated
   // component kept its rank writes only the pieces holding that rank.
   constexpr bool kSuffixShared = SF > NR;
   if (valid) store_mix<M, C, S, SF, true, kSuffixShared>(m, blk, p);
   if (slow) {
-    if constexpr (((SF + L.vpc - 1) / L.vpc) * L.vpc < NR) store_rows_from<M, C, S, SF>(m, blk, p);
+    if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF>(m, blk, p);
     if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, kept < 0, kept);
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
@@ -128,7 +128,7 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
     wave_bytes += n_slow * 2u * kFull;
   } else {
     // read everything; write the rows, and the whole suffix or rank `kept`'s pieces of it
-    wave_bytes += n_slow * (kFull + L.npc * kChunkBytes) + __popcll(__ballot(slow && kept < 0)) * L.sb;
+    wave_bytes += n_slow * (kFull + P::hot) + __popcll(__ballot(slow && kept < 0)) * P::sb;
     static_for<0, M>([&](auto r_) RGBD_BODY {
       constexpr int r = RGBD_I(r_);
       wave_bytes += __popcll(__ballot(slow && kept == r)) * suffix_rank_bytes<M, C, S>(r);
@@ -149,7 +149,7 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   bool fgc = false, fgd = false;
   uint32_t wave_bytes = 0;
   if (AUG && (mode & kModeAug) != 0) {
-    const StateBlock blk = make_block(a.st_rgb, a.tiles64, tile_layout(M, 4, sizeof(S)));
+    const StateBlock blk = make_block<M, 4, S>(a.st_rgb, a.tiles64);
     Mix<M, 4> m;
     load_prefix<M, 4, S>(m, blk, p, valid);
     const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
@@ -162,8 +162,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
   const bool do_c = (mode & kModeRGB) != 0, do_d = (mode & kModeDepth) != 0, do_f = (mode & kModeFuse) != 0;
-  const StateBlock blk_c = make_block(a.st_rgb, a.tiles64, tile_layout(M, 3, sizeof(S)));
-  const StateBlock blk_d = make_block(a.st_depth, a.tiles64, tile_layout(M, 1, sizeof(S)));
+  const StateBlock blk_c = make_block<M, 3, S>(a.st_rgb, a.tiles64);
+  const StateBlock blk_d = make_block<M, 1, S>(a.st_depth, a.tiles64);
   Mix<M, 3> mc;
   Mix<M, 1> md;
   // Every load of the pixel is issued before any result is used (the state blocks, the fusion

@@ -48,18 +48,17 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
 }
 
 // Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks), two-plane
-// layout. (Padding halves of 16-bit suffix words are never read.)
-template <typename S>
-__global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, int M, int C, float var0) {
+// layout. (Padding halves of 16-bit words are never read.)
+template <int M, int C, typename S>
+__global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const uint32_t nv = static_cast<uint32_t>((C + 2) * M);
+  constexpr uint32_t nv = static_cast<uint32_t>((C + 2) * M);
   const int64_t total = static_cast<int64_t>(nv) * kWave * tiles64;
   if (i >= total) return;
   const uint32_t lane = static_cast<uint32_t>(i % kWave);
   const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
   const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
-  const uint64_t byte = state_value_offset(v, static_cast<uint64_t>(tile) * kWave + lane, tiles64,
-                                           static_cast<uint32_t>(M), static_cast<uint32_t>(C), sizeof(S));
+  const uint64_t byte = value_offset<M, C, S>(v, static_cast<uint64_t>(tile) * kWave + lane, tiles64);
   // value order: M weights, then per rank (variance, C means)
   const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
   *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(is_var ? var0 : 0.f);
@@ -123,16 +122,38 @@ hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, ui
   return hipGetLastError();
 }
 
-hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s) {
-  const int64_t total = static_cast<int64_t>(C + 2) * M * kWave * tiles64;
-  const dim3 g = grid_for(total), b(kBlock);
+template <int M, int C>
+static void init_mc(void* st, int dtype, uint32_t tiles64, float var0, dim3 g, hipStream_t s) {
   switch (dtype) {
-    case GMM_F32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float*>(st), tiles64, M, C, var0); break;
-    case GMM_F16: init_kernel<f16s><<<g, b, 0, s>>>(static_cast<f16s*>(st), tiles64, M, C, var0); break;
-    case GMM_BF16: init_kernel<bf16s><<<g, b, 0, s>>>(static_cast<bf16s*>(st), tiles64, M, C, var0); break;
+    case GMM_F32: init_kernel<M, C, float><<<g, dim3(kBlock), 0, s>>>(static_cast<float*>(st), tiles64, var0); break;
+    case GMM_F16: init_kernel<M, C, f16s><<<g, dim3(kBlock), 0, s>>>(static_cast<f16s*>(st), tiles64, var0); break;
+    default: init_kernel<M, C, bf16s><<<g, dim3(kBlock), 0, s>>>(static_cast<bf16s*>(st), tiles64, var0); break;
+  }
+}
+
+template <int C>
+static hipError_t init_c(void* st, int dtype, uint32_t tiles64, int M, float var0, dim3 g, hipStream_t s) {
+  switch (M) {
+    case 1: init_mc<1, C>(st, dtype, tiles64, var0, g, s); break;
+    case 2: init_mc<2, C>(st, dtype, tiles64, var0, g, s); break;
+    case 3: init_mc<3, C>(st, dtype, tiles64, var0, g, s); break;
+    case 4: init_mc<4, C>(st, dtype, tiles64, var0, g, s); break;
+    case 5: init_mc<5, C>(st, dtype, tiles64, var0, g, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s) {
+  if (dtype != GMM_F32 && dtype != GMM_F16 && dtype != GMM_BF16) return hipErrorInvalidValue;
+  const int64_t total = static_cast<int64_t>(C + 2) * M * kWave * tiles64;
+  const dim3 g = grid_for(total);
+  switch (C) {
+    case 1: return init_c<1>(st, dtype, tiles64, M, var0, g, s);
+    case 3: return init_c<3>(st, dtype, tiles64, M, var0, g, s);
+    case 4: return init_c<4>(st, dtype, tiles64, M, var0, g, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {

@@ -1,9 +1,9 @@
 // Host-side check of the two-plane state layout (no GPU needed): for every compiled (M, C,
 // value size) and a block of a few tiles, every value of every pixel has its own aligned bytes
-// inside the block, the chunk rows of all tiles come first (row c of tile t at t*npc KB + c KB),
-// the suffix of each pixel is contiguous at cold + p*sb, the fast-path prefix lies in the chunk
-// rows whenever whole chunks can hold it, and the fast path's stores cover only values its loads
-// read.
+// inside the block, the hot rows of all tiles come first (row c of tile t at t*64*hot + off[c],
+// lane L at + L*width[c]), rows are 16, 8 or 4 bytes per lane and end exactly at the fast path's
+// store and load counts (to the 32-bit word), the suffix of each pixel is contiguous at
+// cold + p*sb, and the fast path's stores cover only values its loads read.
 #include <cstdio>
 #include <vector>
 
@@ -11,12 +11,14 @@
 
 using namespace rgbd;
 
+static uint32_t round_words(uint32_t values, uint32_t es) { return (values * es + 3u) / 4u * 4u; }
+
 template <int M, int C, typename S>
 static int check() {
   constexpr uint32_t es = sizeof(S), nv = (C + 2) * M;
   constexpr TileLayout L = tile_layout(M, C, es);
   constexpr uint64_t tiles = 3;
-  const uint64_t block = tiles * L.bytes, cold = tiles * L.npc * kRowBytes;
+  const uint64_t block = tiles * L.bytes, cold = tiles * 64u * L.hot;
   int bad = 0;
   std::vector<int64_t> owner(block, -1);
   for (uint64_t p = 0; p < tiles * 64; ++p)
@@ -35,15 +37,32 @@ static int check() {
         }
         owner[off + b] = static_cast<int64_t>(p * nv + v);
       }
-      const uint32_t nf = L.npc * L.vpc;
-      if (v >= nf && off != cold + p * L.sb + (v - nf) * es) ++bad;
-      if (v < nf && off != (p / 64) * L.npc * kRowBytes + (v / L.vpc) * kRowBytes + (p % 64) * kChunkBytes +
-                               (v % L.vpc) * es)
-        ++bad;
+      if (value_offset<M, C, S>(v, p, tiles) != off) ++bad;  // the device code's offset agrees
+      if (v >= L.nf && off != cold + p * L.sb + (v - L.nf) * es) ++bad;
+      if (v < L.nf) {
+        uint32_t c = 0;
+        while (L.first[c + 1] <= v) ++c;
+        if (off != (p / 64) * 64u * L.hot + L.off[c] + (p % 64) * L.width[c] + (v - L.first[c]) * es) ++bad;
+      }
     }
-  if (L.sb % 4 || L.npc * kRowBytes + 64 * L.sb != L.bytes || L.rest * es > L.sb) ++bad;
-  const uint32_t lf = fast_load_count(M, C);
-  if (L.npc * L.vpc < lf && L.npc != nv / L.vpc) ++bad;   // prefix in rows whenever it fits
+  uint32_t hot = 0;
+  for (uint32_t c = 0; c < L.nrows; ++c) {
+    if (L.width[c] != 16 && L.width[c] != 8 && L.width[c] != 4) ++bad;
+    if (L.off[c] != 64u * hot || (L.first[c + 1] - L.first[c]) * es > L.width[c]) ++bad;
+    hot += L.width[c];
+  }
+  if (hot != L.hot || L.sb % 4 || 64u * (L.hot + L.sb) != L.bytes || L.rest * es > L.sb || L.nf + L.rest != nv) ++bad;
+  // the rows end where the fast path's stores end and where its loads end (whole words)
+  const uint32_t sf = fast_store_count(M, C), lf = fast_load_count(M, C);
+  bool store_end = false, load_end = false;
+  for (uint32_t c = 0; c <= L.nrows; ++c) {
+    if (64u * round_words(sf, es) == L.off[c]) store_end = true;
+    if (64u * round_words(lf, es) == L.off[c]) load_end = true;
+  }
+  if (!store_end || !load_end) {
+    std::printf("M=%d C=%d es=%u: rows do not end at the fast store (%u) and load (%u) counts\n", M, C, es, sf, lf);
+    ++bad;
+  }
   if (!stores_only_read<M, C, kFastLoad<M, C>, kFastStore<M, C>, S>()) ++bad;
   return bad;
 }

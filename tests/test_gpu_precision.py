@@ -113,3 +113,57 @@ def test_reduced_precision_report():
             batches[d].close()
             for s in segs[d]:
                 s.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_lockstep_reduced_precision_full_size_sampled(dtype):
+    """fp16 / bf16 state at the 256-stream workload's full shape (640x480, M=5), four streams in one
+    batched launch over the 120-frame clip. At checkpoint frames both sides start from the same
+    state - the device's own, read back exactly - on 2048 sampled pixels per stream (and the
+    ragged end): the oracle, rounding every stored value to the storage type, takes the frame,
+    the batched launch takes it for the whole frame, and every sampled parameter must agree within
+    one storage ulp, every mask bit except where the oracle's decision was within the lockstep
+    margins."""
+    from tests.parity import excused
+    from tests.test_gpu_parity import _ulp_mismatch
+    wl = workload("precision-256")
+    mix = wl.mix
+    specs = wl.streams[:4]
+    streams = [Stream(s) for s in specs]
+    segs = [Segmenter(s.width, s.height, GMM_RGB | GMM_DEPTH, mix.M, state_dtype=dtype) for s in specs]
+    batch = Batch(segs)
+    n = specs[0].npix
+    rng = np.random.default_rng(29)
+    samples = [np.unique(np.concatenate([rng.choice(n, 2048, replace=False), np.arange(n - 64, n)])) for _ in specs]
+    checkpoints = {0, 1, 30, 75, 119}
+    checked = 0
+    try:
+        for t in range(wl.frames):
+            frames = [(st.rgb(t, device=DEV), st.depth(t, device=DEV)) for st in streams]
+            if t not in checkpoints:
+                batch.apply(frames, fuse=False)
+                continue
+            before = [from_canonical(s.read_state(), mix.M, n, True, True) for s in segs]
+            batch.apply(frames, fuse=False)
+            torch.cuda.synchronize()
+            for i, st in enumerate(streams):
+                pix = samples[i]
+                tp = torch.from_numpy(pix)
+                for m, C, x in (("rgb", 3, st.rgb(t, pix=tp).numpy()), ("depth", 1, st.depth(t, pix=tp).numpy())):
+                    o = MixtureOracle(_params(mix, m), C, pix.size, storage=dtype)
+                    o.set_state(*(a[..., pix] for a in before[i][m]))
+                    info = o.step(x)
+                    after = from_canonical(segs[i].read_state(), mix.M, n, True, True)[m]
+                    got = tuple(a[..., pix] for a in after)
+                    ex = excused(info)
+                    bad = _ulp_mismatch(got, (o.mu, o.var, o.w), dtype) & ~ex
+                    assert not np.any(bad), (dtype, t, i, m, np.flatnonzero(bad)[:8])
+                    g = unpack_mask(segs[i].fg_rgb if m == "rgb" else segs[i].fg_depth, n)[pix]
+                    assert not np.any((g != info.fg) & ~ex), (dtype, t, i, m)
+                    checked += pix.size
+        print(f"LOCKSTEP_FULL {dtype}: {checked} sampled pixel-steps within one storage ulp", flush=True)
+    finally:
+        batch.close()
+        for s in segs:
+            s.close()
