@@ -485,15 +485,29 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     if (!present) continue;
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
-    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, static_cast<uint32_t>(h->esize)).bytes;
+    const uint32_t es = static_cast<uint32_t>(h->esize);
+    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, es).bytes;
+    // scaled weights: the weight is the scale times the scaled weight (a product of two floats,
+    // exact in double)
+    std::vector<double> scale;
+    if (scaled_weights(es)) {
+      try {
+        scale.resize(n);
+      } catch (...) {
+        return fail(GMM_ERR_OUT_OF_MEMORY, "host staging buffer");
+      }
+      for (size_t i = 0; i < n; ++i)
+        unpack_values(raw.data() + off + state_value_offset(kScaleIndex, i, h->tiles64, static_cast<uint32_t>(M), C, es),
+                      &scale[i], 1, h->cfg.state_dtype);
+    }
     // two-plane device layout -> canonical [param][rank][pixel]
     for (size_t k = 0; k < P * M; ++k) {
-      const uint32_t v = value_index(static_cast<uint32_t>(k / M), static_cast<uint32_t>(k % M),
-                                     static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
+      const uint32_t param = static_cast<uint32_t>(k / M);
+      const uint32_t v = value_index(param, static_cast<uint32_t>(k % M), static_cast<uint32_t>(M), C, es);
       for (size_t i = 0; i < n; ++i) {
-        const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C,
-                                                   static_cast<uint32_t>(h->esize));
+        const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C, es);
         unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
+        if (param == C + 1 && !scale.empty()) o[i] *= scale[i];
       }
       o += n;
     }
@@ -525,14 +539,21 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     if (!present) continue;
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
-    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, static_cast<uint32_t>(h->esize)).bytes;
+    const uint32_t es = static_cast<uint32_t>(h->esize);
+    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, es).bytes;
+    // scaled weights are written with scale 1
+    if (scaled_weights(es)) {
+      const double one = 1.0;
+      for (size_t i = 0; i < n; ++i)
+        pack_values(&one, raw.data() + off + state_value_offset(kScaleIndex, i, h->tiles64, static_cast<uint32_t>(M), C, es),
+                    1, h->cfg.state_dtype);
+    }
     // canonical [param][rank][pixel] -> two-plane device layout
     for (size_t k = 0; k < P * M; ++k) {
       const uint32_t v = value_index(static_cast<uint32_t>(k / M), static_cast<uint32_t>(k % M),
-                                     static_cast<uint32_t>(M), static_cast<uint32_t>(P - 2));
+                                     static_cast<uint32_t>(M), C, es);
       for (size_t i = 0; i < n; ++i) {
-        const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C,
-                                                   static_cast<uint32_t>(h->esize));
+        const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C, es);
         pack_values(in + i, raw.data() + at, 1, h->cfg.state_dtype);
       }
       in += n;

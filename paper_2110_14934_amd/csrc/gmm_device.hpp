@@ -85,32 +85,61 @@ template <> struct Storage<bf16s> {
 };
 
 // ---- the mixture of one pixel ----------------------------------------------------------
+// Weights are held in one of two forms, fixed by the storage type:
+//   direct (16-bit storage): w[r] is the weight itself;
+//   scaled (fp32 storage):   w[r] is a scaled weight w'_r and the weight is g * w'_r, with one
+//                            positive scale g per pixel. A frame multiplies every weight by
+//                            (1 - alpha); in this form that is g <- g (1 - alpha), and only the
+//                            updated component's w' changes, so a frame that keeps the pixel on
+//                            its top component writes g and rank 0 and leaves the other ranks'
+//                            weights untouched in memory.
 template <int M, int C>
 struct Mix {
   float mu[C][M];
   float var[M];
   float w[M];
+  float g;  // scale of the weights (scaled form only)
 };
 
-// Order of a pixel's NV = (C+2)*M values: the M weights first, then rank by rank the variance
-// and the C means. The values a frame needs when the pixel matches its top-ranked component and
-// keeps its rank - every weight, rank 0, and rank 1's variance - are then a prefix.
-__host__ __device__ constexpr uint32_t value_index(uint32_t param, uint32_t rank, uint32_t M, uint32_t C) {
-  // param: 0..C-1 = mean channel, C = variance, C+1 = weight
-  return param == C + 1 ? rank : M + rank * (C + 1) + (param == C ? 0 : 1 + param);
+__host__ __device__ constexpr bool scaled_weights(uint32_t es) { return es == 4; }
+template <typename S>
+constexpr bool kScaled = scaled_weights(sizeof(S));
+
+// Number of stored values per pixel: (C+2)*M, plus the scale in the scaled form.
+__host__ __device__ constexpr uint32_t value_count(uint32_t M, uint32_t C, uint32_t es) {
+  return (C + 2) * M + (scaled_weights(es) ? 1u : 0u);
 }
 
-// Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
-// it: all weights, rank 0 (variance, means) and the variance of rank 1 ...
-__host__ __device__ constexpr uint32_t fast_load_count(uint32_t M, uint32_t C) {
-  return M > 1 ? M + (C + 1) + 1 : M + (C + 1);
+// Order of a pixel's values.
+//   direct: the M weights first, then rank by rank the variance and the C means;
+//   scaled: the scale g first, then rank by rank the scaled weight, the variance and the C means.
+// The values a frame needs when the pixel matches its top-ranked component and keeps its rank
+// are then a prefix: every weight, rank 0 and rank 1's variance (direct); g, rank 0, and rank
+// 1's scaled weight and variance (scaled).
+__host__ __device__ constexpr uint32_t value_index(uint32_t param, uint32_t rank, uint32_t M, uint32_t C,
+                                                   uint32_t es) {
+  // param: 0..C-1 = mean channel, C = variance, C+1 = weight
+  if (scaled_weights(es)) return 1 + rank * (C + 2) + (param == C + 1 ? 0 : (param == C ? 1 : 2 + param));
+  return param == C + 1 ? rank : M + rank * (C + 1) + (param == C ? 0 : 1 + param);
 }
-// ... and the values such a frame changes: all weights and rank 0.
-__host__ __device__ constexpr uint32_t fast_store_count(uint32_t M, uint32_t C) { return M + (C + 1); }
-template <int M, int C>
-constexpr int kFastLoad = static_cast<int>(fast_load_count(M, C));
-template <int M, int C>
-constexpr int kFastStore = static_cast<int>(fast_store_count(M, C));
+constexpr uint32_t kScaleIndex = 0;  // the scale's value index (scaled form)
+
+// Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
+// it come after the values such a frame changes; both sets are prefixes of the value order.
+//   direct: changes every weight and rank 0; also reads rank 1's variance;
+//   scaled: changes g and rank 0; also reads rank 1's scaled weight and variance.
+__host__ __device__ constexpr uint32_t fast_store_count(uint32_t M, uint32_t C, uint32_t es) {
+  return scaled_weights(es) ? 1 + (C + 2) : M + (C + 1);
+}
+__host__ __device__ constexpr uint32_t fast_load_count(uint32_t M, uint32_t C, uint32_t es) {
+  return fast_store_count(M, C, es) + (M > 1 ? (scaled_weights(es) ? 2u : 1u) : 0u);
+}
+template <int M, int C, typename S>
+constexpr int kFastLoad = static_cast<int>(fast_load_count(M, C, sizeof(S)));
+template <int M, int C, typename S>
+constexpr int kFastStore = static_cast<int>(fast_store_count(M, C, sizeof(S)));
+template <int M, int C, typename S>
+constexpr int kNV = static_cast<int>(value_count(M, C, sizeof(S)));
 
 // One modality's state block as a buffer resource, in two planes. Pixels are grouped in tiles
 // of 64 (one wave); each pixel has NV = (C+2)*M values (in value_index order).
@@ -150,8 +179,8 @@ struct TileLayout {
 // value left alone shares its word with the next value, or with padding past the last one).
 __host__ __device__ constexpr TileLayout tile_layout(uint32_t M, uint32_t C, uint32_t es) {
   TileLayout L{};
-  const uint32_t nv = (C + 2) * M;
-  const uint32_t ends[2] = {fast_store_count(M, C), fast_load_count(M, C)};
+  const uint32_t nv = value_count(M, C, es);
+  const uint32_t ends[2] = {fast_store_count(M, C, es), fast_load_count(M, C, es)};
   uint32_t v = 0;
   for (uint32_t seg = 0; seg < 2; ++seg) {
     const uint32_t end = ends[seg] < nv ? ends[seg] : nv;
@@ -305,7 +334,7 @@ __host__ __device__ constexpr bool value_read(uint32_t v) {
 // Every value a store of [0, SF) writes is one a load of [0, LF) read.
 template <int M, int C, int LF, int SF, typename S>
 __host__ __device__ constexpr bool stores_only_read() {
-  for (uint32_t v = 0; v < static_cast<uint32_t>((C + 2) * M); ++v)
+  for (uint32_t v = 0; v < static_cast<uint32_t>(kNV<M, C, S>); ++v)
     if (value_read<M, C, SF, S>(v) && !value_read<M, C, LF, S>(v)) return false;
   return true;
 }
@@ -331,9 +360,18 @@ __host__ __device__ constexpr bool rows_from_exist() {
 }
 
 // Value V (in value_index order) of a pixel's mixture, as the Mix field that holds it.
-template <int M, int C, int V>
+template <int M, int C, typename S, int V>
 __device__ __forceinline__ float& field(Mix<M, C>& m) {
-  if constexpr (V < M) {
+  if constexpr (kScaled<S>) {
+    if constexpr (V == static_cast<int>(kScaleIndex)) {
+      return m.g;
+    } else {
+      constexpr int r = (V - 1) / (C + 2), pos = (V - 1) % (C + 2);
+      if constexpr (pos == 0) return m.w[r];
+      else if constexpr (pos == 1) return m.var[r];
+      else return m.mu[pos - 2][r];
+    }
+  } else if constexpr (V < M) {
     return m.w[V];
   } else {
     constexpr int r = (V - M) / (C + 1), pos = (V - M) % (C + 1);
@@ -341,28 +379,36 @@ __device__ __forceinline__ float& field(Mix<M, C>& m) {
     else return m.mu[pos - 1][r];
   }
 }
-template <int M, int C, int V>
+template <int M, int C, typename S, int V>
 __device__ __forceinline__ float field(const Mix<M, C>& m) {
-  return field<M, C, V>(const_cast<Mix<M, C>&>(m));
+  return field<M, C, S, V>(const_cast<Mix<M, C>&>(m));
+}
+
+// What a value not read is left at: 1 for a variance and for the scale (so that keys stay
+// finite), 0 otherwise.
+template <int M, int C, typename S, int V>
+__host__ __device__ constexpr float unread_value() {
+  if constexpr (kScaled<S>) return (V == static_cast<int>(kScaleIndex) || (V - 1) % (C + 2) == 1) ? 1.f : 0.f;
+  else return (V >= M && (V - M) % (C + 1) == 0) ? 1.f : 0.f;
 }
 
 // Value V, or 0 past the last value (the padding half of a 16-bit word).
-template <int M, int C, int V>
+template <int M, int C, typename S, int V>
 __device__ __forceinline__ float value_or_pad(const Mix<M, C>& m) {
-  if constexpr (V < (C + 2) * M) return field<M, C, V>(m);
+  if constexpr (V < kNV<M, C, S>) return field<M, C, S, V>(m);
   else return 0.f;
 }
 
 // Row c of pixel p into the Mix (values past the last one are padding and dropped).
 template <int M, int C, typename S, int c>
 __device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane) {
-  constexpr int NV = (C + 2) * M, vpw = 4 / static_cast<int>(sizeof(S));
+  constexpr int NV = kNV<M, C, S>, vpw = 4 / static_cast<int>(sizeof(S));
   constexpr uint32_t W = Plan<M, C, S>::L.width[c], off = Plan<M, C, S>::L.off[c];
   constexpr int v0 = static_cast<int>(Plan<M, C, S>::L.first[c]);
   const RowWords<W> o = load_row<W>(b.rsrc, base + off + lane * W);
   static_for<0, static_cast<int>(W / sizeof(S))>([&](auto i_) RGBD_BODY {
     constexpr int i = RGBD_I(i_);
-    if constexpr (v0 + i < NV) field<M, C, v0 + i>(m) = BufIO<S>::from_word(o.w[i / vpw], i % vpw);
+    if constexpr (v0 + i < NV) field<M, C, S, v0 + i>(m) = BufIO<S>::from_word(o.w[i / vpw], i % vpw);
   });
 }
 
@@ -375,7 +421,7 @@ __device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& 
   RowWords<W> o{};
   static_for<0, static_cast<int>(W / 4)>([&](auto k_) RGBD_BODY {
     constexpr int k = RGBD_I(k_);
-    o.w[k] = BufIO<S>::word(value_or_pad<M, C, v0 + k * vpw>(m), value_or_pad<M, C, v0 + k * vpw + vpw - 1>(m));
+    o.w[k] = BufIO<S>::word(value_or_pad<M, C, S, v0 + k * vpw>(m), value_or_pad<M, C, S, v0 + k * vpw + vpw - 1>(m));
   });
   store_row<W>(o, b.rsrc, base + off + lane * W);
 }
@@ -383,16 +429,16 @@ __device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& 
 // Values [0, LIMIT) of pixel p, straight into the Mix (see value_read for what comes along). A
 // value not read is left at 0 - a variance at 1, so that keys stay finite (any use of it is
 // discarded by the caller). LIMIT = NV reads everything.
-template <int M, int C, typename S, int LIMIT = (C + 2) * M>
+template <int M, int C, typename S, int LIMIT = kNV<M, C, S>>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, NV>([&](auto v_) RGBD_BODY {
     constexpr int v = RGBD_I(v_);
-    if constexpr (!value_read<M, C, LIMIT, S>(v)) field<M, C, v>(m) = (v >= M && (v - M) % (C + 1) == 0) ? 1.f : 0.f;
+    if constexpr (!value_read<M, C, LIMIT, S>(v)) field<M, C, S, v>(m) = unread_value<M, C, S, v>();
   });
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
@@ -407,7 +453,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
       static_for<0, 4 * vpw>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         constexpr int v = nf + (4 * g) * vpw + i;
-        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
+        if constexpr (v < NV) field<M, C, S, v>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
       });
     });
     static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
@@ -416,7 +462,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
       static_for<0, vpw>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         constexpr int v = nf + wi * vpw + i;
-        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w, i);
+        if constexpr (v < NV) field<M, C, S, v>(m) = BufIO<S>::from_word(w, i);
       });
     });
   }
@@ -427,7 +473,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
 // the Mix holds the whole state.
 template <int M, int C, typename S, int LF>
 __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
-  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t lane = p & 63u;
@@ -444,7 +490,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
       static_for<0, 4 * vpw>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         constexpr int v = nf + (4 * g) * vpw + i;
-        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
+        if constexpr (v < NV) field<M, C, S, v>(m) = BufIO<S>::from_word(w[i / vpw], i % vpw);
       });
     });
     static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
@@ -453,7 +499,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
       static_for<0, vpw>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         constexpr int v = nf + wi * vpw + i;
-        if constexpr (v < NV) field<M, C, v>(m) = BufIO<S>::from_word(w, i);
+        if constexpr (v < NV) field<M, C, S, v>(m) = BufIO<S>::from_word(w, i);
       });
     });
   }
@@ -462,7 +508,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
 // Values [0, LIMIT) of pixel p from the Mix (whole rows and the whole suffix, as load_mix reads
 // them). ROWS / SUFFIX select the parts written, so that a caller can store the rows of every
 // lane with one instruction per row and the suffix of some lanes only.
-template <int M, int C, typename S, int LIMIT = (C + 2) * M, bool ROWS = true, bool SUFFIX = true>
+template <int M, int C, typename S, int LIMIT = kNV<M, C, S>, bool ROWS = true, bool SUFFIX = true>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
   constexpr int es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
@@ -481,14 +527,14 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
       static_for<0, 4>([&](auto i_) RGBD_BODY {
         constexpr int i = RGBD_I(i_);
         constexpr int v = nf + (4 * g + i) * vpw;
-        w[i] = BufIO<S>::word(value_or_pad<M, C, v>(m), value_or_pad<M, C, v + vpw - 1>(m));
+        w[i] = BufIO<S>::word(value_or_pad<M, C, S, v>(m), value_or_pad<M, C, S, v + vpw - 1>(m));
       });
       __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, sbase + 16u * g, 0, 0);
     });
     static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
       constexpr int wi = RGBD_I(w_);
       constexpr int v = nf + wi * vpw;
-      const uint32_t w = BufIO<S>::word(value_or_pad<M, C, v>(m), value_or_pad<M, C, v + vpw - 1>(m));
+      const uint32_t w = BufIO<S>::word(value_or_pad<M, C, S, v>(m), value_or_pad<M, C, S, v + vpw - 1>(m));
       __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, sbase + 4u * wi, 0, 0);
     });
   }
@@ -507,11 +553,13 @@ __device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateB
   });
 }
 
-// Whether values [a, e) include one of rank r's (its variance or a mean).
-template <int M, int C>
+// Whether values [a, e) include one of rank r's (its variance or a mean; in the scaled form also
+// its scaled weight).
+template <int M, int C, typename S>
 __host__ __device__ constexpr bool holds_rank(int a, int e, int r) {
-  const int lo = M + r * (C + 1);
-  return lo < e && lo + C + 1 > a;
+  const int lo = kScaled<S> ? 1 + r * (C + 2) : M + r * (C + 1);
+  const int n = kScaled<S> ? C + 2 : C + 1;
+  return lo < e && lo + n > a;
 }
 
 // Suffix bytes one lane writes with store_suffix_of when only rank r changed there.
@@ -521,8 +569,8 @@ __host__ __device__ constexpr uint32_t suffix_rank_bytes(int r) {
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   uint32_t n = 0;
-  for (int g = 0; g < nw / 4; ++g) n += holds_rank<M, C>(nf + 4 * g * vpw, nf + (4 * g + 4) * vpw, r) ? 16u : 0u;
-  for (int wi = (nw / 4) * 4; wi < nw; ++wi) n += holds_rank<M, C>(nf + wi * vpw, nf + (wi + 1) * vpw, r) ? 4u : 0u;
+  for (int g = 0; g < nw / 4; ++g) n += holds_rank<M, C, S>(nf + 4 * g * vpw, nf + (4 * g + 4) * vpw, r) ? 16u : 0u;
+  for (int wi = (nw / 4) * 4; wi < nw; ++wi) n += holds_rank<M, C, S>(nf + wi * vpw, nf + (wi + 1) * vpw, r) ? 4u : 0u;
   return n;
 }
 
@@ -533,14 +581,14 @@ __host__ __device__ constexpr uint32_t suffix_rank_bytes(int r) {
 // request of a lane.
 template <int M, int C, typename S>
 __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool all, int r) {
-  constexpr int NV = (C + 2) * M, es = sizeof(S), vpw = 4 / es;
+  constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t sbase = b.cold + p * P::sb;
-  const int lo = M + r * (C + 1), hi = lo + C + 1;
+  const int lo = kScaled<S> ? 1 + r * (C + 2) : M + r * (C + 1), hi = lo + (kScaled<S> ? C + 2 : C + 1);
   auto sv = [&](auto v_) RGBD_BODY -> float {
     constexpr int v = RGBD_I(v_);
-    if constexpr (v < NV) return field<M, C, v>(m);
+    if constexpr (v < NV) return field<M, C, S, v>(m);
     else return 0.f;
   };
   static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
@@ -566,11 +614,17 @@ __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateB
   });
 }
 
+// The smallest scale the scaled form keeps; below it (and at alpha = 1, where the scale becomes
+// 0) the scale is folded into the weights and the step renormalises them as plain weights.
+constexpr float kMinScale = 2.3283064365386963e-10f;  // 2^-32
+
 // The matched component's new mean, variance and weight (from the values before the update and
-// the squared distance d2j of x to its mean); shared by mix_step and fast_step.
-template <int C>
+// the squared distance d2j of x to its mean); shared by mix_step and fast_step. Direct weights:
+// w <- (1 - alpha) w + alpha. Scaled weights: w' <- w' + inc with inc = alpha / g_new, which
+// with g_new = (1 - alpha) g is the same update of g * w'.
+template <int C, bool SCALED>
 __device__ __forceinline__ void update_matched(float (&mj)[C], float& vj, float& wj, float d2j, const float (&x)[C],
-                                               const ModelConsts& k) {
+                                               const ModelConsts& k, float inc) {
   float d2n = 0.f;
   if (k.rho_density) {  // uniform over the wave
     // rho = alpha (2 pi var)^(-C/2) exp(-d2 / (2 var)), with exp(y) = 2^(y log2 e); the
@@ -595,7 +649,8 @@ __device__ __forceinline__ void update_matched(float (&mj)[C], float& vj, float&
     });
     vj = fmaxf(k.var_min, fmaf(k.oma, vj, k.alpha * d2n));
   }
-  wj = fmaf(k.oma, wj, k.alpha);
+  if constexpr (SCALED) wj = wj + inc;
+  else wj = fmaf(k.oma, wj, k.alpha);
 }
 
 // Weights after the decay (w_old scaled by 1 - alpha, rank t set to tw), renormalised to sum to
@@ -616,8 +671,10 @@ __device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const floa
 }
 
 // One frame of the mixture model for one pixel (Sec. III.A with the update rules of the
-// paper's reference [6]). Returns the foreground bit; `j_out` is the matched rank (M if none)
-// and `q_out` the rank the updated (or new) component ends up at.
+// paper's reference [6]). Returns the foreground bit; `j_out` is the matched rank (M if none),
+// `q_out` the rank the updated (or new) component ends up at, and `all_out` whether every
+// stored weight changed (the scaled form's fold-back; otherwise only rank q's weight and, in the
+// scaled form, the scale).
 //   match    : first live rank, in stored (w/sigma descending) order, with |x-mu|^2 < k^2 var
 //   weights  : w <- (1-alpha) w + alpha [matched]
 //   matched  : mu <- (1-rho) mu + rho x ; var <- max(var_min, (1-rho) var + rho |x-mu_new|^2), with
@@ -626,14 +683,18 @@ __device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const floa
 //   no match : the last rank becomes (x, sigma0^2, w_init)
 //   then     : w <- w / sum(w); re-sort by w/sigma descending; B = min{b : w_0+...+w_{b-1} > T};
 //              foreground = no match or new rank >= B
+// Scaled weights (SCALED): the decay of every weight is g <- (1-alpha) g. After a match the
+// weights still sum to one, so the renormalisation changes nothing and only the matched w'
+// moves; after a replacement the scale takes it, g = 1 / sum(w'). Keys compare w'/sigma, the same
+// order as w/sigma (one positive scale per pixel).
 // Re-sort: the renormalisation scales every unchanged weight by the same factor, so the
 // unchanged components keep their order and only the updated one (t) can be out of place. It
 // walks up past neighbours with a strictly smaller key and down past neighbours with a strictly
 // larger key - the stable sort of the stored order. The walk stops at the first neighbour it may
 // not pass, so ranks beyond that neighbour are never consulted.
-template <int M, int C>
+template <int M, int C, bool SCALED>
 __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], const ModelConsts& k, int& j_out,
-                                         int& q_out) {
+                                         int& q_out, bool& all_out) {
   // match, in rank order
   int j = M;
   float d2j = 0.f;  // squared distance to the matched component
@@ -666,16 +727,44 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       mj[c] = pick(isj, s.mu[c][r], mj[c]);
     });
   });
-  update_matched<C>(mj, vj, wj, d2j, x, k);
+  const float wj_old = wj;
+  float g1 = 1.f, inc = 0.f;
+  bool fold = false;
+  if constexpr (SCALED) {
+    g1 = s.g * k.oma;
+    fold = !(g1 >= kMinScale);
+    inc = k.alpha / g1;
+  }
+  update_matched<C, SCALED>(mj, vj, wj, d2j, x, k, inc);
   // no match: the least probable (last-ranked) component is replaced
   float tmu[C];
   static_for<0, C>([&](auto c_) RGBD_BODY { tmu[RGBD_I(c_)] = pick(matched, mj[RGBD_I(c_)], x[RGBD_I(c_)]); });
   const float tvar = pick(matched, vj, k.var0);
-  float tw = pick(matched, wj, k.w_init);
+  float tw = pick(matched, wj, SCALED ? k.w_init / g1 : k.w_init);
 
   // decay of the other weights, renormalisation of all
   float w[M];
-  renormalise<M>(w, tw, s.w, t, k.oma);
+  float gn = 1.f;
+  if constexpr (SCALED) {
+    if (!fold) {
+      float sum = 0.f;
+      static_for<0, M>([&](auto r_) RGBD_BODY {
+#pragma clang fp contract(off)
+        constexpr int r = RGBD_I(r_);
+        w[r] = pick(r == t, tw, s.w[r]);
+        sum += w[r];
+      });
+      gn = matched ? g1 : 1.0f / sum;
+    } else {
+      // the weights as plain weights (g * w'), decayed, updated and renormalised; scale 1
+      float wt[M];
+      static_for<0, M>([&](auto r_) RGBD_BODY { wt[RGBD_I(r_)] = s.g * s.w[RGBD_I(r_)]; });
+      tw = matched ? fmaf(k.oma, s.g * wj_old, k.alpha) : k.w_init;
+      renormalise<M>(w, tw, wt, t, k.oma);
+    }
+  } else {
+    renormalise<M>(w, tw, s.w, t, k.oma);
+  }
 
   // re-sort: walk the changed component to its place
   const float kt = tw * __builtin_amdgcn_rsqf(tvar);
@@ -715,6 +804,7 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       o.mu[c][r] = pick(r == q, tmu[c], mv);
     });
   });
+  o.g = gn;
   s = o;
 
   // background set: the first B ranks whose cumulative weight exceeds T
@@ -722,21 +812,24 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
   float run = 0.f;
   static_for<0, M>([&](auto r_) RGBD_BODY {
     constexpr int r = RGBD_I(r_);
-    run += s.w[r];
+    run += SCALED ? gn * s.w[r] : s.w[r];
     B = (B == M && run > k.T) ? r + 1 : B;
   });
   j_out = j;
   q_out = q;
+  all_out = fold;
   return !matched || q >= B;
 }
 
 // The frame of a pixel whose rank-0 component matches x and keeps rank 0, on the values
-// load_prefix reads (all weights, rank 0, rank 1's variance). For such a pixel it computes
-// exactly what mix_step computes (same helpers, same order), far more cheaply: no gather over
-// the ranks, no permutation, and the pixel is background (rank 0 < B, since B >= 1). Returns
-// whether the pixel is such a pixel; if not, `s` holds partial results and the caller runs
-// mix_step on the whole state instead.
-template <int M, int C>
+// load_prefix reads (direct: all weights, rank 0, rank 1's variance; scaled: the scale, rank 0,
+// rank 1's scaled weight and variance). For such a pixel it computes exactly what mix_step
+// computes (same helpers, same order), far more cheaply: no gather over the ranks, no
+// permutation, and the pixel is background (rank 0 < B, since B >= 1). Returns whether the pixel
+// is such a pixel; if not, `s` holds partial results and the caller runs mix_step on the whole
+// state instead. In the scaled form a scale that would fall below kMinScale also sends the pixel
+// to mix_step, which folds it into the weights.
+template <int M, int C, bool SCALED>
 __device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], const ModelConsts& k) {
   float d2 = 0.f;
   static_for<0, C>([&](auto c_) RGBD_BODY {
@@ -744,19 +837,30 @@ __device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], con
     const float t = x[c] - s.mu[c][0];
     d2 = fmaf(t, t, d2);
   });
-  const bool hit = (s.w[0] > 0.f) & (d2 < k.k2 * s.var[0]);
+  bool hit = (s.w[0] > 0.f) & (d2 < k.k2 * s.var[0]);
   float mj[C], vj = s.var[0], wj = s.w[0];
   static_for<0, C>([&](auto c_) RGBD_BODY { mj[RGBD_I(c_)] = s.mu[RGBD_I(c_)][0]; });
-  update_matched<C>(mj, vj, wj, d2, x, k);
-  float w[M];
-  renormalise<M>(w, wj, s.w, 0, k.oma);
+  float g1 = 1.f, inc = 0.f;
+  if constexpr (SCALED) {
+    g1 = s.g * k.oma;
+    hit = hit & (g1 >= kMinScale);
+    inc = k.alpha / g1;
+  }
+  update_matched<C, SCALED>(mj, vj, wj, d2, x, k, inc);
   // rank 0 keeps its place unless rank 1's key is strictly larger
   bool keeps = true;
-  if constexpr (M > 1) keeps = !(w[1] * __builtin_amdgcn_rsqf(s.var[1]) > wj * __builtin_amdgcn_rsqf(vj));
+  if constexpr (SCALED) {
+    if constexpr (M > 1) keeps = !(s.w[1] * __builtin_amdgcn_rsqf(s.var[1]) > wj * __builtin_amdgcn_rsqf(vj));
+    s.g = g1;
+  } else {
+    float w[M];
+    renormalise<M>(w, wj, s.w, 0, k.oma);
+    if constexpr (M > 1) keeps = !(w[1] * __builtin_amdgcn_rsqf(s.var[1]) > wj * __builtin_amdgcn_rsqf(vj));
+    static_for<1, M>([&](auto r_) RGBD_BODY { s.w[RGBD_I(r_)] = w[RGBD_I(r_)]; });
+  }
   static_for<0, C>([&](auto c_) RGBD_BODY { s.mu[RGBD_I(c_)][0] = mj[RGBD_I(c_)]; });
   s.var[0] = vj;
   s.w[0] = wj;
-  static_for<1, M>([&](auto r_) RGBD_BODY { s.w[RGBD_I(r_)] = w[RGBD_I(r_)]; });
   return hit & keeps;
 }
 

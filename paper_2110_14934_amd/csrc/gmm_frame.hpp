@@ -72,18 +72,20 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
 }
 
 // The values a frame needs when the pixel matches its rank-0 component and that component keeps
-// its rank: all weights, rank 0 and rank 1's variance (the fast-path prefix, in the chunk rows).
+// its rank (the fast-path prefix, in the hot rows): all weights, rank 0 and rank 1's variance
+// (direct weights), or the scale, rank 0 and rank 1's scaled weight and variance (scaled).
 template <int M, int C, typename S>
 __device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid) {
-  if (valid) load_mix<M, C, S, kFastLoad<M, C>>(m, blk, p);
+  if (valid) load_mix<M, C, S, kFastLoad<M, C, S>>(m, blk, p);
 }
 
 // One modality of pixel p, with lazy state traffic decided lane by lane, on the prefix in `m`.
 // fast_step is the step specialised to the case above; a lane for which that case holds writes
-// back only the weights and rank 0. Any other lane keeps the prefix as read, loads the rest of
-// its state, runs the full step from the original values and writes back what changed: the
-// chunk rows, and the whole suffix when the ranks were reordered, else only the suffix pieces
-// of the rank the updated component kept. fast_step computes exactly what the full step
+// back only the values that case changes (the weights and rank 0, or the scale and rank 0). Any
+// other lane keeps the prefix as read, loads the rest of its state, runs the full step from the
+// original values and writes back what changed: the hot rows, and the whole suffix when the
+// ranks were reordered (or every scaled weight changed), else only the suffix pieces of the rank
+// the updated component kept. fast_step computes exactly what the full step
 // computes for such a pixel, so results never depend on which path ran. `valid` lanes hold a
 // pixel; `active` lanes update it (a depth hole is valid but not active: it writes back what it
 // read). Returns the foreground bit; adds the state bytes the wave's lanes read and wrote to
@@ -92,22 +94,23 @@ template <int M, int C, typename S>
 __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
                                               bool active, const float (&x)[C], const ModelConsts& k,
                                               uint32_t& wave_bytes) {
-  constexpr int NV = (C + 2) * M;
-  constexpr int LF = kFastLoad<M, C>;
-  constexpr int SF = kFastStore<M, C>;
+  constexpr int NV = kNV<M, C, S>;
+  constexpr int LF = kFastLoad<M, C, S>;
+  constexpr int SF = kFastStore<M, C, S>;
   static_assert(stores_only_read<M, C, LF, SF, S>(), "the fast path writes back a value it did not read");
   using P = Plan<M, C, S>;
   constexpr int NR = static_cast<int>(P::nf);  // values held by the hot rows
   bool fg = false;
   const Mix<M, C> read = m;  // the prefix as read (fast_step updates m in place)
-  const bool slow = active && !fast_step<M, C>(m, x, k);
+  const bool slow = active && !fast_step<M, C, kScaled<S>>(m, x, k);
   int kept = -1;  // the rank the updated component kept, or -1 when the ranks were reordered
   if (slow) {  // m now holds each lane's own path's values
     m = read;
     load_rest<M, C, S, LF>(m, blk, p);
     int j, q;
-    fg = mix_step<M, C>(m, x, k, j, q);
-    kept = (j < M ? j : M - 1) == q ? q : -1;
+    bool all = false;
+    fg = mix_step<M, C, kScaled<S>>(m, x, k, j, q, all);
+    kept = !all && (j < M ? j : M - 1) == q ? q : -1;
   }
   // Write-back: every piece both paths write goes out in one store for all the lanes that write
   // it (a hot row then leaves the wave as one write, not as one per path). Both paths write the
@@ -177,8 +180,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   if (do_c) rl = issue_rgb_pixel(a, pc, wave_base, lane);
   const float xd = do_d ? load_depth_pixel(a, pc) : 0.f;
   const uint32_t fst = do_f ? a.fstate[pc] : 0u;
-  if (do_c) load_mix<M, 3, S, kFastLoad<M, 3>>(mc, blk_c, pc);
-  if (do_d) load_mix<M, 1, S, kFastLoad<M, 1>>(md, blk_d, pc);
+  if (do_c) load_mix<M, 3, S, kFastLoad<M, 3, S>>(mc, blk_c, pc);
+  if (do_d) load_mix<M, 1, S, kFastLoad<M, 1, S>>(md, blk_d, pc);
   float x[3] = {0.f, 0.f, 0.f};
   if (do_c) finish_rgb_pixel(rl, lane, lds_wave, x);
   if (do_c) {

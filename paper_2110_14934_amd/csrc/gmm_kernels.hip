@@ -47,21 +47,29 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
   if (lane == 0 && valid) out[word] = bits;
 }
 
-// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks), two-plane
-// layout. (Padding halves of 16-bit words are never read.)
+// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks; scale 1 in the
+// scaled form), two-plane layout. (Padding halves of 16-bit words are never read.)
 template <int M, int C, typename S>
 __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  constexpr uint32_t nv = static_cast<uint32_t>((C + 2) * M);
+  constexpr uint32_t nv = value_count(M, C, sizeof(S));
   const int64_t total = static_cast<int64_t>(nv) * kWave * tiles64;
   if (i >= total) return;
   const uint32_t lane = static_cast<uint32_t>(i % kWave);
   const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
   const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
   const uint64_t byte = value_offset<M, C, S>(v, static_cast<uint64_t>(tile) * kWave + lane, tiles64);
-  // value order: M weights, then per rank (variance, C means)
-  const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
-  *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(is_var ? var0 : 0.f);
+  // value order: direct - M weights, then per rank (variance, C means); scaled - the scale, then
+  // per rank (scaled weight, variance, C means)
+  float init = 0.f;
+  if constexpr (kScaled<S>) {
+    const bool is_var = v != kScaleIndex && (v - 1) % (C + 2) == 1;
+    init = v == kScaleIndex ? 1.f : (is_var ? var0 : 0.f);
+  } else {
+    const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
+    init = is_var ? var0 : 0.f;
+  }
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(init);
 }
 
 __global__ void __launch_bounds__(kBlock) fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
@@ -146,7 +154,9 @@ static hipError_t init_c(void* st, int dtype, uint32_t tiles64, int M, float var
 
 hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s) {
   if (dtype != GMM_F32 && dtype != GMM_F16 && dtype != GMM_BF16) return hipErrorInvalidValue;
-  const int64_t total = static_cast<int64_t>(C + 2) * M * kWave * tiles64;
+  const int64_t total = static_cast<int64_t>(value_count(static_cast<uint32_t>(M), static_cast<uint32_t>(C),
+                                                         static_cast<uint32_t>(dtype_size(dtype)))) *
+                        kWave * tiles64;
   const dim3 g = grid_for(total);
   switch (C) {
     case 1: return init_c<1>(st, dtype, tiles64, M, var0, g, s);

@@ -15,7 +15,7 @@ static uint32_t round_words(uint32_t values, uint32_t es) { return (values * es 
 
 template <int M, int C, typename S>
 static int check() {
-  constexpr uint32_t es = sizeof(S), nv = (C + 2) * M;
+  constexpr uint32_t es = sizeof(S), nv = value_count(M, C, es);
   constexpr TileLayout L = tile_layout(M, C, es);
   constexpr uint64_t tiles = 3;
   const uint64_t block = tiles * L.bytes, cold = tiles * 64u * L.hot;
@@ -53,7 +53,7 @@ static int check() {
   }
   if (hot != L.hot || L.sb % 4 || 64u * (L.hot + L.sb) != L.bytes || L.rest * es > L.sb || L.nf + L.rest != nv) ++bad;
   // the rows end where the fast path's stores end and where its loads end (whole words)
-  const uint32_t sf = fast_store_count(M, C), lf = fast_load_count(M, C);
+  const uint32_t sf = fast_store_count(M, C, es), lf = fast_load_count(M, C, es);
   bool store_end = false, load_end = false;
   for (uint32_t c = 0; c <= L.nrows; ++c) {
     if (64u * round_words(sf, es) == L.off[c]) store_end = true;
@@ -63,7 +63,14 @@ static int check() {
     std::printf("M=%d C=%d es=%u: rows do not end at the fast store (%u) and load (%u) counts\n", M, C, es, sf, lf);
     ++bad;
   }
-  if (!stores_only_read<M, C, kFastLoad<M, C>, kFastStore<M, C>, S>()) ++bad;
+  if (!stores_only_read<M, C, kFastLoad<M, C, S>, kFastStore<M, C, S>, S>()) ++bad;
+  // every (parameter, rank) has its own value, and the scaled form's scale one more
+  std::vector<int> seen(nv, 0);
+  for (uint32_t param = 0; param < C + 2; ++param)
+    for (uint32_t r = 0; r < M; ++r) ++seen[value_index(param, r, M, C, es)];
+  if (scaled_weights(es)) ++seen[kScaleIndex];
+  for (uint32_t v = 0; v < nv; ++v)
+    if (seen[v] != 1) ++bad;
   return bad;
 }
 
