@@ -197,9 +197,10 @@ gmm_status rgbd::new_handle(const gmm_config* cfg, gmm_handle** out) {
   h->esize = dtype_size(cfg->state_dtype);
   const uint32_t M = static_cast<uint32_t>(cfg->M), es = static_cast<uint32_t>(h->esize);
   const size_t tiles = h->tiles64;
-  h->rgb_bytes = is_augmented(h) ? tiles * tile_layout(M, 4, es).bytes
-                                 : (has_rgb(h) ? tiles * tile_layout(M, 3, es).bytes : 0);
-  h->depth_bytes = sep_depth(h) ? tiles * tile_layout(M, 1, es).bytes : 0;
+  // each block rounded up to 256 bytes, so that the next one starts aligned
+  h->rgb_bytes = is_augmented(h) ? round_up(tiles * tile_layout(M, 4, es).bytes, 256)
+                                 : (has_rgb(h) ? round_up(tiles * tile_layout(M, 3, es).bytes, 256) : 0);
+  h->depth_bytes = sep_depth(h) ? round_up(tiles * tile_layout(M, 1, es).bytes, 256) : 0;
   h->fuse_bytes = sep_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
   if (std::max(h->rgb_bytes, h->depth_bytes) > 0xFFFFFFFFull) {
     delete h;
@@ -486,19 +487,18 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
     const uint32_t es = static_cast<uint32_t>(h->esize);
-    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, es).bytes;
-    // scaled weights: the weight is the scale times the scaled weight (a product of two floats,
-    // exact in double)
+    // scaled weights: the weight is the tile's scale times the scaled weight (a product of two
+    // floats, exact in double)
     std::vector<double> scale;
     if (scaled_weights(es)) {
       try {
-        scale.resize(n);
+        scale.resize(h->tiles64);
       } catch (...) {
         return fail(GMM_ERR_OUT_OF_MEMORY, "host staging buffer");
       }
-      for (size_t i = 0; i < n; ++i)
-        unpack_values(raw.data() + off + state_value_offset(kScaleIndex, i, h->tiles64, static_cast<uint32_t>(M), C, es),
-                      &scale[i], 1, h->cfg.state_dtype);
+      for (size_t t = 0; t < h->tiles64; ++t)
+        unpack_values(raw.data() + off + state_scale_offset(t, h->tiles64, static_cast<uint32_t>(M), C, es),
+                      &scale[t], 1, h->cfg.state_dtype);
     }
     // two-plane device layout -> canonical [param][rank][pixel]
     for (size_t k = 0; k < P * M; ++k) {
@@ -507,11 +507,11 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
       for (size_t i = 0; i < n; ++i) {
         const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C, es);
         unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
-        if (param == C + 1 && !scale.empty()) o[i] *= scale[i];
+        if (param == C + 1 && !scale.empty()) o[i] *= scale[i / kWave];
       }
       o += n;
     }
-    off += tile_bytes * h->tiles64;
+    off += blk == 0 ? h->rgb_bytes : h->depth_bytes;
   }
   if (sep_both(h)) {
     const uint8_t* f = raw.data() + off;
@@ -540,13 +540,12 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
     const uint32_t es = static_cast<uint32_t>(h->esize);
-    const size_t tile_bytes = tile_layout(static_cast<uint32_t>(M), C, es).bytes;
-    // scaled weights are written with scale 1
+    // scaled weights are written with scale 1 (rank 1's key is computed on the device below)
     if (scaled_weights(es)) {
       const double one = 1.0;
-      for (size_t i = 0; i < n; ++i)
-        pack_values(&one, raw.data() + off + state_value_offset(kScaleIndex, i, h->tiles64, static_cast<uint32_t>(M), C, es),
-                    1, h->cfg.state_dtype);
+      for (size_t t = 0; t < h->tiles64; ++t)
+        pack_values(&one, raw.data() + off + state_scale_offset(t, h->tiles64, static_cast<uint32_t>(M), C, es), 1,
+                    h->cfg.state_dtype);
     }
     // canonical [param][rank][pixel] -> two-plane device layout
     for (size_t k = 0; k < P * M; ++k) {
@@ -558,7 +557,7 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
       }
       in += n;
     }
-    off += tile_bytes * h->tiles64;
+    off += blk == 0 ? h->rgb_bytes : h->depth_bytes;
   }
   if (sep_both(h)) {
     uint8_t* f = raw.data() + off;
@@ -575,6 +574,9 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
   if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(h->mem, raw.data(), total, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && has_rgb(h))
+    e = launch_rekey(h->st_rgb, h->cfg.state_dtype, h->tiles64, h->cfg.M, is_augmented(h) ? 4 : 3, s);
+  if (e == hipSuccess && sep_depth(h)) e = launch_rekey(h->st_depth, h->cfg.state_dtype, h->tiles64, h->cfg.M, 1, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "state copy to device");
   h->last_stream = s;

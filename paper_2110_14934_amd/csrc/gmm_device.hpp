@@ -88,51 +88,67 @@ template <> struct Storage<bf16s> {
 // Weights are held in one of two forms, fixed by the storage type:
 //   direct (16-bit storage): w[r] is the weight itself;
 //   scaled (fp32 storage):   w[r] is a scaled weight w'_r and the weight is g * w'_r, with one
-//                            positive scale g per pixel. A frame multiplies every weight by
-//                            (1 - alpha); in this form that is g <- g (1 - alpha), and only the
-//                            updated component's w' changes, so a frame that keeps the pixel on
-//                            its top component writes g and rank 0 and leaves the other ranks'
-//                            weights untouched in memory.
+//                            positive scale g shared by the 64 pixels of a tile (stored once per
+//                            tile). A frame multiplies every weight by (1 - alpha); in this form
+//                            that is g <- g (1 - alpha), once per tile, and only the updated
+//                            component's w' changes, so a frame that keeps a pixel on its top
+//                            component writes rank 0 alone. The form also stores the key of rank
+//                            1 (key1 = w'_1 / sigma_1, as the re-sort computes it), which such a
+//                            frame compares with rank 0's new key and never changes.
 template <int M, int C>
 struct Mix {
   float mu[C][M];
   float var[M];
   float w[M];
-  float g;  // scale of the weights (scaled form only)
+  float g;     // the tile's scale of the weights (scaled form only)
+  float key1;  // rank 1's key w'_1 / sigma_1 as stored (scaled form only)
 };
 
 __host__ __device__ constexpr bool scaled_weights(uint32_t es) { return es == 4; }
 template <typename S>
 constexpr bool kScaled = scaled_weights(sizeof(S));
 
-// Number of stored values per pixel: (C+2)*M, plus the scale in the scaled form.
+// Number of stored values per pixel: (C+2)*M, plus rank 1's key in the scaled form.
 __host__ __device__ constexpr uint32_t value_count(uint32_t M, uint32_t C, uint32_t es) {
-  return (C + 2) * M + (scaled_weights(es) ? 1u : 0u);
+  return (C + 2) * M + (scaled_weights(es) && M > 1 ? 1u : 0u);
+}
+
+// First value of rank r's component: direct - its variance (the weights come first, apart);
+// scaled - its scaled weight (rank 0's values, then rank 1's key, then ranks 1.. M-1).
+__host__ __device__ constexpr uint32_t rank_first(uint32_t rank, uint32_t M, uint32_t C, uint32_t es) {
+  if (scaled_weights(es)) return rank * (C + 2) + (rank > 0 ? 1u : 0u);
+  return M + rank * (C + 1);
+}
+// Values of rank r stored from rank_first on.
+__host__ __device__ constexpr uint32_t rank_values(uint32_t C, uint32_t es) {
+  return scaled_weights(es) ? C + 2 : C + 1;
 }
 
 // Order of a pixel's values.
 //   direct: the M weights first, then rank by rank the variance and the C means;
-//   scaled: the scale g first, then rank by rank the scaled weight, the variance and the C means.
+//   scaled: rank 0's scaled weight, variance and C means, rank 1's key, then rank by rank
+//           (1 .. M-1) the scaled weight, the variance and the C means.
 // The values a frame needs when the pixel matches its top-ranked component and keeps its rank
-// are then a prefix: every weight, rank 0 and rank 1's variance (direct); g, rank 0, and rank
-// 1's scaled weight and variance (scaled).
+// are then a prefix: every weight, rank 0 and rank 1's variance (direct); rank 0 and rank 1's
+// key (scaled).
 __host__ __device__ constexpr uint32_t value_index(uint32_t param, uint32_t rank, uint32_t M, uint32_t C,
                                                    uint32_t es) {
   // param: 0..C-1 = mean channel, C = variance, C+1 = weight
-  if (scaled_weights(es)) return 1 + rank * (C + 2) + (param == C + 1 ? 0 : (param == C ? 1 : 2 + param));
-  return param == C + 1 ? rank : M + rank * (C + 1) + (param == C ? 0 : 1 + param);
+  if (scaled_weights(es)) return rank_first(rank, M, C, es) + (param == C + 1 ? 0 : (param == C ? 1 : 2 + param));
+  return param == C + 1 ? rank : rank_first(rank, M, C, es) + (param == C ? 0 : 1 + param);
 }
-constexpr uint32_t kScaleIndex = 0;  // the scale's value index (scaled form)
+// rank 1's key (scaled form, M > 1)
+__host__ __device__ constexpr uint32_t key_index(uint32_t C) { return C + 2; }
 
 // Values that are only read (not written) by the frame of a pixel that matches rank 0 and keeps
 // it come after the values such a frame changes; both sets are prefixes of the value order.
 //   direct: changes every weight and rank 0; also reads rank 1's variance;
-//   scaled: changes g and rank 0; also reads rank 1's scaled weight and variance.
+//   scaled: changes rank 0; also reads rank 1's key.
 __host__ __device__ constexpr uint32_t fast_store_count(uint32_t M, uint32_t C, uint32_t es) {
-  return scaled_weights(es) ? 1 + (C + 2) : M + (C + 1);
+  return scaled_weights(es) ? C + 2 : M + (C + 1);
 }
 __host__ __device__ constexpr uint32_t fast_load_count(uint32_t M, uint32_t C, uint32_t es) {
-  return fast_store_count(M, C, es) + (M > 1 ? (scaled_weights(es) ? 2u : 1u) : 0u);
+  return fast_store_count(M, C, es) + (M > 1 ? 1u : 0u);
 }
 template <int M, int C, typename S>
 constexpr int kFastLoad = static_cast<int>(fast_load_count(M, C, sizeof(S)));
@@ -141,8 +157,8 @@ constexpr int kFastStore = static_cast<int>(fast_store_count(M, C, sizeof(S)));
 template <int M, int C, typename S>
 constexpr int kNV = static_cast<int>(value_count(M, C, sizeof(S)));
 
-// One modality's state block as a buffer resource, in two planes. Pixels are grouped in tiles
-// of 64 (one wave); each pixel has NV = (C+2)*M values (in value_index order).
+// One modality's state block as a buffer resource, in two planes (three in the scaled form).
+// Pixels are grouped in tiles of 64 (one wave); each pixel has NV values (in value_index order).
 //   hot plane  - rows holding the values a steady-state frame touches, tile after tile. Row c
 //                holds values [first[c], first[c+1]) of the tile's 64 lanes as [lane][width[c]]
 //                with width[c] = 16, 8 or 4 bytes, so one wave instruction moves 1 KB, 512 B or
@@ -153,7 +169,8 @@ constexpr int kNV = static_cast<int>(value_count(M, C, sizeof(S)));
 //   cold plane - after the hot plane of all tiles: the remaining values of each pixel,
 //                contiguous per pixel and padded to whole 32-bit words (sb bytes), pixel p's at
 //                cold + p*sb. A pixel that leaves the fast path reads and writes its suffix as a
-//                few contiguous bytes.
+//                few contiguous bytes;
+//   scale plane - scaled form: after the cold plane, the scale g of each tile (4 bytes).
 // A frame whose pixels keep to the fast path therefore streams through one dense plane and
 // skips the other. A lane's offsets are a VGPR plus compile-time constants, so each state access
 // is one buffer instruction. The range checked by the hardware (num_records) is the whole block:
@@ -171,7 +188,8 @@ struct TileLayout {
   uint32_t nf = 0;                   // values held by the hot rows
   uint32_t rest = 0;                 // values per pixel in the cold plane
   uint32_t sb = 0;                   // cold bytes per pixel (whole 32-bit words)
-  uint32_t bytes = 0;                // bytes per tile of 64 pixels: 64 * (hot + sb)
+  uint32_t scale = 0;                // scale-plane bytes per tile (4 in the scaled form, else 0)
+  uint32_t bytes = 0;                // bytes per tile of 64 pixels: 64 * (hot + sb) + scale
 };
 
 // Rows covering values [0, fast_store_count) and then [fast_store_count, fast_load_count), each
@@ -200,7 +218,8 @@ __host__ __device__ constexpr TileLayout tile_layout(uint32_t M, uint32_t C, uin
   L.off[L.nrows] = 64u * L.hot;
   L.rest = nv - L.nf;
   L.sb = (L.rest * es + 3u) / 4u * 4u;
-  L.bytes = 64u * (L.hot + L.sb);
+  L.scale = scaled_weights(es) ? 4u : 0u;
+  L.bytes = 64u * (L.hot + L.sb) + L.scale;
   return L;
 }
 
@@ -211,6 +230,13 @@ struct Plan {
   // the scalars device code uses, so that no layout object is ever built at run time
   static constexpr uint32_t nrows = L.nrows, hot = L.hot, nf = L.nf, sb = L.sb, bytes = L.bytes;
 };
+
+// Byte offset, inside a block of `tiles64` tiles, of the scale of tile `tile` (scaled form).
+__host__ __device__ constexpr uint64_t state_scale_offset(uint64_t tile, uint64_t tiles64, uint32_t M, uint32_t C,
+                                                          uint32_t es) {
+  const TileLayout L = tile_layout(M, C, es);
+  return tiles64 * 64u * (L.hot + L.sb) + 4u * tile;
+}
 
 // Byte offset, inside a block of `tiles64` tiles, of value v of pixel p.
 __host__ __device__ constexpr uint64_t state_value_offset(uint32_t v, uint64_t p, uint64_t tiles64, uint32_t M,
@@ -241,13 +267,24 @@ struct StateBlock {
   __amdgpu_buffer_rsrc_t rsrc;
   uint32_t tile_rows;  // hot bytes per tile: 64 * hot
   uint32_t cold;       // byte offset of the cold plane
+  uint32_t scale;      // byte offset of the scale plane (scaled form)
 };
 
 template <int M, int C, typename S>
 __device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64) {
   using P = Plan<M, C, S>;
   return StateBlock{__builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(P::bytes * tiles64), kRsrcWord3),
-                    64u * P::hot, tiles64 * 64u * P::hot};
+                    64u * P::hot, tiles64 * 64u * P::hot, tiles64 * 64u * (P::hot + P::sb)};
+}
+
+// The scale of the tile holding pixel p (scaled form), the same for every lane of the wave. It
+// stays a per-lane value: moving it to a scalar register would make the wave wait for every load
+// issued before it, right after issuing them.
+__device__ __forceinline__ float load_scale(const StateBlock& b, uint32_t p) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, b.scale + 4u * (p >> 6), 0, 0));
+}
+__device__ __forceinline__ void store_scale(float g, const StateBlock& b, uint32_t p) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, g), b.rsrc, b.scale + 4u * (p >> 6), 0, 0);
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -363,10 +400,10 @@ __host__ __device__ constexpr bool rows_from_exist() {
 template <int M, int C, typename S, int V>
 __device__ __forceinline__ float& field(Mix<M, C>& m) {
   if constexpr (kScaled<S>) {
-    if constexpr (V == static_cast<int>(kScaleIndex)) {
-      return m.g;
+    if constexpr (M > 1 && V == static_cast<int>(key_index(C))) {
+      return m.key1;
     } else {
-      constexpr int r = (V - 1) / (C + 2), pos = (V - 1) % (C + 2);
+      constexpr int r = V < C + 2 ? 0 : (V - 1) / (C + 2), pos = V < C + 2 ? V : (V - 1) % (C + 2);
       if constexpr (pos == 0) return m.w[r];
       else if constexpr (pos == 1) return m.var[r];
       else return m.mu[pos - 2][r];
@@ -384,12 +421,15 @@ __device__ __forceinline__ float field(const Mix<M, C>& m) {
   return field<M, C, S, V>(const_cast<Mix<M, C>&>(m));
 }
 
-// What a value not read is left at: 1 for a variance and for the scale (so that keys stay
-// finite), 0 otherwise.
+// What a value not read is left at: 1 for a variance (so that keys stay finite), 0 otherwise.
 template <int M, int C, typename S, int V>
 __host__ __device__ constexpr float unread_value() {
-  if constexpr (kScaled<S>) return (V == static_cast<int>(kScaleIndex) || (V - 1) % (C + 2) == 1) ? 1.f : 0.f;
-  else return (V >= M && (V - M) % (C + 1) == 0) ? 1.f : 0.f;
+  if constexpr (kScaled<S>) {
+    if constexpr (M > 1 && V == static_cast<int>(key_index(C))) return 0.f;
+    else return (V < C + 2 ? V : (V - 1) % (C + 2)) == 1 ? 1.f : 0.f;
+  } else {
+    return (V >= M && (V - M) % (C + 1) == 0) ? 1.f : 0.f;
+  }
 }
 
 // Value V, or 0 past the last value (the padding half of a 16-bit word).
@@ -557,8 +597,8 @@ __device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateB
 // its scaled weight).
 template <int M, int C, typename S>
 __host__ __device__ constexpr bool holds_rank(int a, int e, int r) {
-  const int lo = kScaled<S> ? 1 + r * (C + 2) : M + r * (C + 1);
-  const int n = kScaled<S> ? C + 2 : C + 1;
+  const int lo = static_cast<int>(rank_first(r, M, C, sizeof(S)));
+  const int n = static_cast<int>(rank_values(C, sizeof(S)));
   return lo < e && lo + n > a;
 }
 
@@ -585,7 +625,7 @@ __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateB
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
   const uint32_t sbase = b.cold + p * P::sb;
-  const int lo = kScaled<S> ? 1 + r * (C + 2) : M + r * (C + 1), hi = lo + (kScaled<S> ? C + 2 : C + 1);
+  const int lo = static_cast<int>(rank_first(r, M, C, sizeof(S))), hi = lo + static_cast<int>(rank_values(C, sizeof(S)));
   auto sv = [&](auto v_) RGBD_BODY -> float {
     constexpr int v = RGBD_I(v_);
     if constexpr (v < NV) return field<M, C, S, v>(m);
@@ -617,6 +657,13 @@ __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateB
 // The smallest scale the scaled form keeps; below it (and at alpha = 1, where the scale becomes
 // 0) the scale is folded into the weights and the step renormalises them as plain weights.
 constexpr float kMinScale = 2.3283064365386963e-10f;  // 2^-32
+
+// The tile's scale after a frame that starts at scale g: g (1 - alpha), or 1 when that falls
+// below kMinScale (the fold). Every pixel of the tile, whatever its path, ends at this value.
+__device__ __forceinline__ float next_scale(float g, const ModelConsts& k) {
+  const float g1 = g * k.oma;
+  return g1 >= kMinScale ? g1 : 1.f;
+}
 
 // The matched component's new mean, variance and weight (from the values before the update and
 // the squared distance d2j of x to its mean); shared by mix_step and fast_step. Direct weights:
@@ -673,8 +720,8 @@ __device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const floa
 // One frame of the mixture model for one pixel (Sec. III.A with the update rules of the
 // paper's reference [6]). Returns the foreground bit; `j_out` is the matched rank (M if none),
 // `q_out` the rank the updated (or new) component ends up at, and `all_out` whether every
-// stored weight changed (the scaled form's fold-back; otherwise only rank q's weight and, in the
-// scaled form, the scale).
+// stored scaled weight changed (the scaled form's replacement and fold-back; otherwise only rank
+// q's weight, and in the direct form the weights, which all sit in the hot rows).
 //   match    : first live rank, in stored (w/sigma descending) order, with |x-mu|^2 < k^2 var
 //   weights  : w <- (1-alpha) w + alpha [matched]
 //   matched  : mu <- (1-rho) mu + rho x ; var <- max(var_min, (1-rho) var + rho |x-mu_new|^2), with
@@ -683,10 +730,11 @@ __device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const floa
 //   no match : the last rank becomes (x, sigma0^2, w_init)
 //   then     : w <- w / sum(w); re-sort by w/sigma descending; B = min{b : w_0+...+w_{b-1} > T};
 //              foreground = no match or new rank >= B
-// Scaled weights (SCALED): the decay of every weight is g <- (1-alpha) g. After a match the
-// weights still sum to one, so the renormalisation changes nothing and only the matched w'
-// moves; after a replacement the scale takes it, g = 1 / sum(w'). Keys compare w'/sigma, the same
-// order as w/sigma (one positive scale per pixel).
+// Scaled weights (SCALED): the decay of every weight is g <- (1-alpha) g, the tile's scale. After
+// a match the weights still sum to one, so the renormalisation changes nothing and only the
+// matched w' moves; after a replacement every w' is divided by g * sum(w'). Keys compare
+// w'/sigma, the same order as w/sigma (one positive scale per pixel). The new scale is left in
+// s.g and rank 1's key in s.key1.
 // Re-sort: the renormalisation scales every unchanged weight by the same factor, so the
 // unchanged components keep their order and only the updated one (t) can be out of place. It
 // walks up past neighbours with a strictly smaller key and down past neighbours with a strictly
@@ -754,7 +802,11 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
         w[r] = pick(r == t, tw, s.w[r]);
         sum += w[r];
       });
-      gn = matched ? g1 : 1.0f / sum;
+      // after a replacement the weights g1 * w' sum to g1 * sum: divide every w' by that
+      const float inv = matched ? 1.0f : 1.0f / (g1 * sum);
+      static_for<0, M>([&](auto r_) RGBD_BODY { w[RGBD_I(r_)] *= inv; });
+      tw = tw * inv;
+      gn = g1;
     } else {
       // the weights as plain weights (g * w'), decayed, updated and renormalised; scale 1
       float wt[M];
@@ -805,6 +857,7 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
     });
   });
   o.g = gn;
+  if constexpr (SCALED && M > 1) o.key1 = o.w[1] * __builtin_amdgcn_rsqf(o.var[1]);
   s = o;
 
   // background set: the first B ranks whose cumulative weight exceeds T
@@ -817,13 +870,25 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
   });
   j_out = j;
   q_out = q;
-  all_out = fold;
+  all_out = SCALED && (fold || !matched);
   return !matched || q >= B;
 }
 
+// The frame of a pixel that keeps its state (a depth hole), in the scaled form: the tile's scale
+// still moves to g (1 - alpha) (or folds to 1), so every w' is rescaled by the old scale over
+// the new one, which keeps each weight g * w'. Rank 1's key follows its w'.
+template <int M, int C>
+__device__ __forceinline__ void hold_step(Mix<M, C>& s, const ModelConsts& k) {
+  const float gn = next_scale(s.g, k);
+  const float f = s.g / gn;
+  static_for<0, M>([&](auto r_) RGBD_BODY { s.w[RGBD_I(r_)] *= f; });
+  s.g = gn;
+  if constexpr (M > 1) s.key1 = s.w[1] * __builtin_amdgcn_rsqf(s.var[1]);
+}
+
 // The frame of a pixel whose rank-0 component matches x and keeps rank 0, on the values
-// load_prefix reads (direct: all weights, rank 0, rank 1's variance; scaled: the scale, rank 0,
-// rank 1's scaled weight and variance). For such a pixel it computes exactly what mix_step
+// load_prefix reads (direct: all weights, rank 0, rank 1's variance; scaled: the tile's scale,
+// rank 0 and rank 1's stored key). For such a pixel it computes exactly what mix_step
 // computes (same helpers, same order), far more cheaply: no gather over the ranks, no
 // permutation, and the pixel is background (rank 0 < B, since B >= 1). Returns whether the pixel
 // is such a pixel; if not, `s` holds partial results and the caller runs mix_step on the whole
@@ -850,7 +915,9 @@ __device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], con
   // rank 0 keeps its place unless rank 1's key is strictly larger
   bool keeps = true;
   if constexpr (SCALED) {
-    if constexpr (M > 1) keeps = !(s.w[1] * __builtin_amdgcn_rsqf(s.var[1]) > wj * __builtin_amdgcn_rsqf(vj));
+    // rank 1's key as mix_step computes it (its w' and variance are unchanged after a match of
+    // rank 0, and a match leaves the weights unscaled)
+    if constexpr (M > 1) keeps = !(s.key1 > wj * __builtin_amdgcn_rsqf(vj));
     s.g = g1;
   } else {
     float w[M];

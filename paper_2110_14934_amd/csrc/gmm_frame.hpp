@@ -73,23 +73,25 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
 
 // The values a frame needs when the pixel matches its rank-0 component and that component keeps
 // its rank (the fast-path prefix, in the hot rows): all weights, rank 0 and rank 1's variance
-// (direct weights), or the scale, rank 0 and rank 1's scaled weight and variance (scaled).
+// (direct weights), or rank 0 and rank 1's key (scaled), and in the scaled form the tile's scale.
 template <int M, int C, typename S>
 __device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid) {
   if (valid) load_mix<M, C, S, kFastLoad<M, C, S>>(m, blk, p);
+  if constexpr (kScaled<S>) m.g = load_scale(blk, p);
 }
 
 // One modality of pixel p, with lazy state traffic decided lane by lane, on the prefix in `m`.
 // fast_step is the step specialised to the case above; a lane for which that case holds writes
-// back only the values that case changes (the weights and rank 0, or the scale and rank 0). Any
-// other lane keeps the prefix as read, loads the rest of its state, runs the full step from the
+// back only the values that case changes (the weights and rank 0, or rank 0 alone). Any other
+// lane keeps the prefix as read, loads the rest of its state, runs the full step from the
 // original values and writes back what changed: the hot rows, and the whole suffix when the
 // ranks were reordered (or every scaled weight changed), else only the suffix pieces of the rank
 // the updated component kept. fast_step computes exactly what the full step
 // computes for such a pixel, so results never depend on which path ran. `valid` lanes hold a
-// pixel; `active` lanes update it (a depth hole is valid but not active: it writes back what it
-// read). Returns the foreground bit; adds the state bytes the wave's lanes read and wrote to
-// `wave_bytes`.
+// pixel; `active` lanes update it (a depth hole is valid but not active: in the direct form it
+// writes back what it read; in the scaled form it rescales its weights to the tile's new scale,
+// hold_step). In the scaled form the tile's first lane then writes the new scale. Returns the
+// foreground bit; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
 template <int M, int C, typename S>
 __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
                                               bool active, const float (&x)[C], const ModelConsts& k,
@@ -100,16 +102,22 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   static_assert(stores_only_read<M, C, LF, SF, S>(), "the fast path writes back a value it did not read");
   using P = Plan<M, C, S>;
   constexpr int NR = static_cast<int>(P::nf);  // values held by the hot rows
+  constexpr bool SC = kScaled<S>;
   bool fg = false;
   const Mix<M, C> read = m;  // the prefix as read (fast_step updates m in place)
-  const bool slow = active && !fast_step<M, C, kScaled<S>>(m, x, k);
+  const bool fast = active && fast_step<M, C, SC>(m, x, k);
+  const bool slow = SC ? valid && !fast : active && !fast;
   int kept = -1;  // the rank the updated component kept, or -1 when the ranks were reordered
   if (slow) {  // m now holds each lane's own path's values
     m = read;
     load_rest<M, C, S, LF>(m, blk, p);
-    int j, q;
-    bool all = false;
-    fg = mix_step<M, C, kScaled<S>>(m, x, k, j, q, all);
+    int j = M, q = M;
+    bool all = true;
+    if (SC && !active) {
+      if constexpr (SC) hold_step<M, C>(m, k);
+    } else {
+      fg = mix_step<M, C, SC>(m, x, k, j, q, all);
+    }
     kept = !all && (j < M ? j : M - 1) == q ? q : -1;
   }
   // Write-back: every piece both paths write goes out in one store for all the lanes that write
@@ -123,6 +131,10 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   if (slow) {
     if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF>(m, blk, p);
     if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, kept < 0, kept);
+  }
+  if constexpr (SC) {  // every valid lane holds the tile's new scale
+    if (valid && (p & 63u) == 0) store_scale(m.g, blk, p);
+    wave_bytes += 8u;
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
   constexpr uint32_t kFull = prefix_bytes<M, C, NV, S>() / kWave;  // a lane's whole state
@@ -180,8 +192,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   if (do_c) rl = issue_rgb_pixel(a, pc, wave_base, lane);
   const float xd = do_d ? load_depth_pixel(a, pc) : 0.f;
   const uint32_t fst = do_f ? a.fstate[pc] : 0u;
-  if (do_c) load_mix<M, 3, S, kFastLoad<M, 3, S>>(mc, blk_c, pc);
-  if (do_d) load_mix<M, 1, S, kFastLoad<M, 1, S>>(md, blk_d, pc);
+  if (do_c) load_prefix<M, 3, S>(mc, blk_c, pc, true);
+  if (do_d) load_prefix<M, 1, S>(md, blk_d, pc, true);
   float x[3] = {0.f, 0.f, 0.f};
   if (do_c) finish_rgb_pixel(rl, lane, lds_wave, x);
   if (do_c) {

@@ -23,8 +23,9 @@ struct FrameArgs {
   int64_t rgb_pitch;
   const uint16_t* depth;
   int64_t depth_pitch;
-  void* st_rgb;            // colour state block: 5*M values per pixel, two planes (four-channel variant: 6*M)
-  void* st_depth;          // depth state block: 3*M values per pixel, two planes
+  void* st_rgb;            // colour state block: 5*M values per pixel (four-channel variant: 6*M), plus rank
+                           // 1's key and one scale per tile in the fp32 form
+  void* st_depth;          // depth state block: 3*M values per pixel (and the same extras)
   uint8_t* fstate;         // List 1 state bytes
   uint64_t* fg_rgb;
   uint64_t* fg_depth;
@@ -43,6 +44,8 @@ hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStrea
 hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, uint8_t* fstate,
                        int64_t npix, hipStream_t s);
 hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s);
+// Rank 1's key of every pixel from the stored values (scaled form; a no-op otherwise).
+hipError_t launch_rekey(void* st, int dtype, uint32_t tiles64, int M, int C, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 
 bool frame_variant_compiled(int M, int dtype);

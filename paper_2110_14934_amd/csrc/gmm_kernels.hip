@@ -47,29 +47,51 @@ __global__ void __launch_bounds__(kBlock) fuse_kernel(const uint64_t* __restrict
   if (lane == 0 && valid) out[word] = bits;
 }
 
-// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks; scale 1 in the
-// scaled form), two-plane layout. (Padding halves of 16-bit words are never read.)
+// Empty components: mu = 0, var = sigma0^2, w = 0 (C+2 parameters x M ranks; in the scaled
+// form rank 1's key 0, which is 0 / sigma0, and the scale of every tile 1), two-plane layout.
+// (Padding halves of 16-bit words are never read.)
 template <int M, int C, typename S>
 __global__ void __launch_bounds__(kBlock) init_kernel(S* st, uint32_t tiles64, float var0) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   constexpr uint32_t nv = value_count(M, C, sizeof(S));
-  const int64_t total = static_cast<int64_t>(nv) * kWave * tiles64;
-  if (i >= total) return;
+  const int64_t values = static_cast<int64_t>(nv) * kWave * tiles64;
+  if constexpr (kScaled<S>) {
+    if (i >= values && i < values + tiles64) {
+      using P = Plan<M, C, S>;  // (constants: a layout object built at run time would live in scratch)
+      const uint64_t byte = static_cast<uint64_t>(tiles64) * 64u * (P::hot + P::sb) + 4u * static_cast<uint64_t>(i - values);
+      *reinterpret_cast<float*>(reinterpret_cast<char*>(st) + byte) = 1.f;
+    }
+  }
+  if (i >= values) return;
   const uint32_t lane = static_cast<uint32_t>(i % kWave);
   const uint32_t v = static_cast<uint32_t>((i / kWave) % nv);
   const int64_t tile = i / (static_cast<int64_t>(kWave) * nv);
   const uint64_t byte = value_offset<M, C, S>(v, static_cast<uint64_t>(tile) * kWave + lane, tiles64);
-  // value order: direct - M weights, then per rank (variance, C means); scaled - the scale, then
-  // per rank (scaled weight, variance, C means)
+  // value order: direct - M weights, then per rank (variance, C means); scaled - rank 0's
+  // (scaled weight, variance, C means), rank 1's key, then the same for ranks 1 .. M-1
   float init = 0.f;
   if constexpr (kScaled<S>) {
-    const bool is_var = v != kScaleIndex && (v - 1) % (C + 2) == 1;
-    init = v == kScaleIndex ? 1.f : (is_var ? var0 : 0.f);
+    const bool key = M > 1 && v == key_index(C);
+    const uint32_t pos = v < C + 2 ? v : (v - 1) % (C + 2);
+    init = !key && pos == 1 ? var0 : 0.f;
   } else {
     const bool is_var = v >= static_cast<uint32_t>(M) && (v - static_cast<uint32_t>(M)) % static_cast<uint32_t>(C + 1) == 0;
     init = is_var ? var0 : 0.f;
   }
   *reinterpret_cast<S*>(reinterpret_cast<char*>(st) + byte) = Storage<S>::pack(init);
+}
+
+// Rank 1's key of every pixel from its stored scaled weight and variance (scaled form, M > 1),
+// computed as the frame kernels compute it: after a state written from the host.
+template <int M, int C>
+__global__ void __launch_bounds__(kBlock) rekey_kernel(float* st, uint32_t tiles64) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= static_cast<int64_t>(tiles64) * kWave) return;
+  char* b = reinterpret_cast<char*>(st);
+  const uint64_t pp = static_cast<uint64_t>(p);
+  const float w1 = *reinterpret_cast<const float*>(b + value_offset<M, C, float>(value_index(C + 1, 1, M, C, 4), pp, tiles64));
+  const float v1 = *reinterpret_cast<const float*>(b + value_offset<M, C, float>(value_index(C, 1, M, C, 4), pp, tiles64));
+  *reinterpret_cast<float*>(b + value_offset<M, C, float>(key_index(C), pp, tiles64)) = w1 * __builtin_amdgcn_rsqf(v1);
 }
 
 __global__ void __launch_bounds__(kBlock) fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
@@ -152,11 +174,37 @@ static hipError_t init_c(void* st, int dtype, uint32_t tiles64, int M, float var
   return hipGetLastError();
 }
 
+template <int C>
+static hipError_t rekey_c(void* st, uint32_t tiles64, int M, dim3 g, hipStream_t s) {
+  float* f = static_cast<float*>(st);
+  switch (M) {
+    case 1: return hipSuccess;  // no rank 1
+    case 2: rekey_kernel<2, C><<<g, dim3(kBlock), 0, s>>>(f, tiles64); break;
+    case 3: rekey_kernel<3, C><<<g, dim3(kBlock), 0, s>>>(f, tiles64); break;
+    case 4: rekey_kernel<4, C><<<g, dim3(kBlock), 0, s>>>(f, tiles64); break;
+    case 5: rekey_kernel<5, C><<<g, dim3(kBlock), 0, s>>>(f, tiles64); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rekey(void* st, int dtype, uint32_t tiles64, int M, int C, hipStream_t s) {
+  if (!scaled_weights(static_cast<uint32_t>(dtype_size(dtype)))) return hipSuccess;
+  const dim3 g = grid_for(static_cast<int64_t>(tiles64) * kWave);
+  switch (C) {
+    case 1: return rekey_c<1>(st, tiles64, M, g, s);
+    case 3: return rekey_c<3>(st, tiles64, M, g, s);
+    case 4: return rekey_c<4>(st, tiles64, M, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s) {
   if (dtype != GMM_F32 && dtype != GMM_F16 && dtype != GMM_BF16) return hipErrorInvalidValue;
-  const int64_t total = static_cast<int64_t>(value_count(static_cast<uint32_t>(M), static_cast<uint32_t>(C),
-                                                         static_cast<uint32_t>(dtype_size(dtype)))) *
-                        kWave * tiles64;
+  const uint32_t es = static_cast<uint32_t>(dtype_size(dtype));
+  const int64_t total = static_cast<int64_t>(value_count(static_cast<uint32_t>(M), static_cast<uint32_t>(C), es)) *
+                            kWave * tiles64 +
+                        (scaled_weights(es) ? tiles64 : 0);
   const dim3 g = grid_for(total);
   switch (C) {
     case 1: return init_c<1>(st, dtype, tiles64, M, var0, g, s);

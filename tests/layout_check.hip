@@ -3,7 +3,8 @@
 // inside the block, the hot rows of all tiles come first (row c of tile t at t*64*hot + off[c],
 // lane L at + L*width[c]), rows are 16, 8 or 4 bytes per lane and end exactly at the fast path's
 // store and load counts (to the 32-bit word), the suffix of each pixel is contiguous at
-// cold + p*sb, and the fast path's stores cover only values its loads read.
+// cold + p*sb, the scaled form's tile scales follow the cold plane one 32-bit word per tile and
+// share no byte with a value, and the fast path's stores cover only values its loads read.
 #include <cstdio>
 #include <vector>
 
@@ -45,13 +46,28 @@ static int check() {
         if (off != (p / 64) * 64u * L.hot + L.off[c] + (p % 64) * L.width[c] + (v - L.first[c]) * es) ++bad;
       }
     }
+  // the tile scales: one aligned word per tile right after the cold plane, inside the block
+  if (L.scale != (scaled_weights(es) ? 4u : 0u)) ++bad;
+  for (uint64_t t = 0; L.scale && t < tiles; ++t) {
+    const uint64_t off = state_scale_offset(t, tiles, M, C, es);
+    if (off % 4 || off != tiles * 64u * (L.hot + L.sb) + 4u * t || off + 4 > block) {
+      ++bad;
+      continue;
+    }
+    for (uint32_t b = 0; b < 4; ++b) {
+      if (owner[off + b] != -1) ++bad;
+      owner[off + b] = -2;
+    }
+  }
   uint32_t hot = 0;
   for (uint32_t c = 0; c < L.nrows; ++c) {
     if (L.width[c] != 16 && L.width[c] != 8 && L.width[c] != 4) ++bad;
     if (L.off[c] != 64u * hot || (L.first[c + 1] - L.first[c]) * es > L.width[c]) ++bad;
     hot += L.width[c];
   }
-  if (hot != L.hot || L.sb % 4 || 64u * (L.hot + L.sb) != L.bytes || L.rest * es > L.sb || L.nf + L.rest != nv) ++bad;
+  if (hot != L.hot || L.sb % 4 || 64u * (L.hot + L.sb) + L.scale != L.bytes || L.rest * es > L.sb ||
+      L.nf + L.rest != nv)
+    ++bad;
   // the rows end where the fast path's stores end and where its loads end (whole words)
   const uint32_t sf = fast_store_count(M, C, es), lf = fast_load_count(M, C, es);
   bool store_end = false, load_end = false;
@@ -64,11 +80,18 @@ static int check() {
     ++bad;
   }
   if (!stores_only_read<M, C, kFastLoad<M, C, S>, kFastStore<M, C, S>, S>()) ++bad;
-  // every (parameter, rank) has its own value, and the scaled form's scale one more
+  // every (parameter, rank) has its own value, and the scaled form's key of rank 1 one more
   std::vector<int> seen(nv, 0);
   for (uint32_t param = 0; param < C + 2; ++param)
-    for (uint32_t r = 0; r < M; ++r) ++seen[value_index(param, r, M, C, es)];
-  if (scaled_weights(es)) ++seen[kScaleIndex];
+    for (uint32_t r = 0; r < M; ++r) {
+      const uint32_t v = value_index(param, r, M, C, es);
+      ++seen[v];
+      // a rank's values lie in [rank_first, rank_first + rank_values)
+      if (v < rank_first(r, M, C, es) || v >= rank_first(r, M, C, es) + rank_values(C, es)) {
+        if (param != C + 1 || scaled_weights(es)) ++bad;  // direct weights sit apart
+      }
+    }
+  if (scaled_weights(es) && M > 1) ++seen[key_index(C)];
   for (uint32_t v = 0; v < nv; ++v)
     if (seen[v] != 1) ++bad;
   return bad;

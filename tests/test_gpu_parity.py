@@ -417,30 +417,31 @@ def test_error_paths_on_device():
         assert e.value.status == _abi.GMM_ERR_INVALID_ARG
         seg.apply(rgb)
         torch.cuda.synchronize()
-        assert seg.state_bytes() == (5 * 3 + 1) * 256 * 4   # fp32: 15 values and the weights' scale
+        # fp32: 15 values and rank 1's key per pixel, a scale per 64-pixel tile, rounded up to 256 B
+        assert seg.state_bytes() == ((5 * 3 + 1) * 256 * 4 + 4 * 4 + 255) // 256 * 256
     finally:
         seg.close()
 
 
 def test_traffic_record_counts_only_the_changed_pieces():
-    """Colour only, M=3, fp32 (scaled weights): a lane's 16 values are 3 hot rows of 16, 8 and
-    8 bytes (the scale and rank 0, which the fast path writes, then rank 1's scaled weight and
-    variance, which it only reads) and a 32-byte suffix (rank 1's means, rank 2) written as two
-    16-byte groups. Frame 0 creates a component that walks from the last rank to rank 0: the
-    whole state is read and written (2 x 64 B). Frame 1 matches rank 0 (fast path: 32 B read,
-    24 B written). Frame 2 (x = 250) matches nothing; the new component takes rank 2 and walks to
-    rank 1: reordered, 128 B. Frames 3 and 4 match rank 1, which keeps its rank (the oracle's
-    j = q = 1): 64 B read, the rows and the one suffix group holding rank 1's means written
-    (32 + 16 B)."""
+    """Colour only, M=3, fp32 (scaled weights): a lane's 16 values are 3 hot rows of 16, 4 and
+    4 bytes (rank 0, which the fast path writes, then rank 1's key, which it only reads) and a
+    40-byte suffix (rank 1, rank 2) written as two 16-byte groups and two words; each frame also
+    reads and writes the tile's scale (8 B per wave). Frame 0 creates a component that walks
+    from the last rank to rank 0: the whole state is read and written (2 x 64 B). Frame 1
+    matches rank 0 (fast path: 24 B read, 20 B written). Frame 2 (x = 250) matches nothing; the
+    new component takes rank 2 and walks to rank 1, and every scaled weight is renormalised:
+    128 B. Frames 3 and 4 match rank 1, which keeps its rank (the oracle's j = q = 1): 64 B
+    read, the rows and the two suffix groups holding rank 1's values written (24 + 32 B)."""
     seg = Segmenter(64, 1, GMM_RGB, 3)
     rec = torch.zeros(1, dtype=torch.int64, device=DEV)
     try:
         _abi.gmm_set_traffic_record(seg.handle, rec)
         want = 0
-        for v, lane_bytes in ((100, 128), (100, 56), (250, 128), (250, 112), (250, 112)):
+        for v, lane_bytes in ((100, 128), (100, 44), (250, 128), (250, 120), (250, 120)):
             seg.apply(torch.full((1, 64, 3), v, dtype=torch.uint8, device=DEV))
             torch.cuda.synchronize()
-            want += 64 * lane_bytes
+            want += 64 * lane_bytes + 8
             assert int(rec[0]) == want, (v, lane_bytes, int(rec[0]), want)
     finally:
         _abi.gmm_set_traffic_record(seg.handle, None)
@@ -448,12 +449,13 @@ def test_traffic_record_counts_only_the_changed_pieces():
 
 
 def test_traffic_record_counts_fast_and_full_lanes():
-    """Traffic is decided per lane (M=5, fp32, scaled weights). Frame 0 matches nothing: every
-    colour lane reads and writes its whole state (2 x 26 values x 4 B = 208 B), every depth lane
-    with a reading too (2 x 16 x 4 B = 128 B), while a depth hole moves only the fast rows (24 B
-    read, 16 B written). The same frame again matches rank 0 everywhere and keeps the order, so
-    every lane moves only the scale and rank 0 (+ rank 1's scaled weight and variance on the read
-    side), exactly: colour 32 + 24 B, depth 24 + 16 B, 64 x 96 = 6144 B per wave."""
+    """Traffic is decided per lane (M=5, fp32, scaled weights; each modality also reads and writes
+    its tile's scale, 2 x 8 B per wave). Frame 0 matches nothing: every colour lane reads and
+    writes its whole state (2 x (26 values x 4 B) = 208 B), every depth lane too (2 x 64 B =
+    128 B; a depth hole rescales its weights to the tile's new scale, which also moves the whole
+    state). The same frame again matches rank 0 everywhere and keeps the order, so every lane
+    with a reading moves only rank 0 (+ rank 1's key on the read side), exactly: colour 24 + 20 B,
+    depth 16 + 12 B; a hole again 128 B."""
     spec = StreamSpec(160, 120, n_boxes=1, box_min=20, box_max=20, hole_p=0.05, seed=61)
     st = Stream(spec)
     seg = Segmenter(160, 120, GMM_RGB | GMM_DEPTH, 5)
@@ -465,14 +467,15 @@ def test_traffic_record_counts_fast_and_full_lanes():
         assert int(holes.sum()) > 0
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        first = 64 * 208 + (64 - holes) * 128 + holes * 40
+        first = torch.full_like(holes, 64 * 208 + 64 * 128 + 16)
         assert torch.equal(rec, first)
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        assert torch.equal(rec, first + 6144)
+        second = first + 64 * 44 + (64 - holes) * 28 + holes * 128 + 16
+        assert torch.equal(rec, second)
         _abi.gmm_set_traffic_record(seg.handle, None)
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        assert torch.equal(rec, first + 6144)
+        assert torch.equal(rec, second)
     finally:
         seg.close()
