@@ -107,7 +107,8 @@ gmm_status gmm_config_default(gmm_config* cfg, int32_t width, int32_t height, in
  * Create a handle: validates `cfg`, allocates the per-pixel state on cfg->device and
  * initialises it synchronously - every component empty (w = 0, mu = 0, var = sigma0^2), and
  * for two-modality handles the fusion state of List 1 at I = 0, cpt = 0.
- * The handle owns all of its device memory. *out is set only on success.
+ * The handle owns all of its device memory. *out is set only on success. Each modality's state
+ * must stay below 2 GiB (GMM_ERR_INVALID_ARG otherwise; fp32, M = 5: about 20 million pixels).
  */
 gmm_status gmm_create(const gmm_config* cfg, gmm_handle** out);
 

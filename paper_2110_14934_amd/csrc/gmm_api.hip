@@ -202,9 +202,10 @@ gmm_status rgbd::new_handle(const gmm_config* cfg, gmm_handle** out) {
                                  : (has_rgb(h) ? round_up(tiles * tile_layout(M, 3, es).bytes, 256) : 0);
   h->depth_bytes = sep_depth(h) ? round_up(tiles * tile_layout(M, 1, es).bytes, 256) : 0;
   h->fuse_bytes = sep_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
-  if (std::max(h->rgb_bytes, h->depth_bytes) > 0xFFFFFFFFull) {
+  // below 2 GiB: the kernels address a block with 32-bit offsets and use offset 2^31 for "no access"
+  if (std::max(h->rgb_bytes, h->depth_bytes) >= 0x80000000ull) {
     delete h;
-    return fail(GMM_ERR_INVALID_ARG, "one modality's state must stay below 4 GiB (too many pixels for this M)");
+    return fail(GMM_ERR_INVALID_ARG, "one modality's state must stay below 2 GiB (too many pixels for this M)");
   }
   if (is_augmented(h)) {
     h->kc = make_consts(*cfg, 0, 4, cfg->hole_policy == GMM_HOLE_SKIP);

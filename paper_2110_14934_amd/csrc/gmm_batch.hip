@@ -40,11 +40,7 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(const FrameArgs* __restric
     const uint32_t s = tile_map[t];
     const FrameArgs a = table[s];
     const uint32_t t0 = (t - first_tile[s]) * tile_px;
-    for (uint32_t sub = 0; sub < tile_px; sub += BLOCK) {
-      const uint32_t base = t0 + sub;
-      if (base >= a.npix) break;  // uniform: the rest of the tile is past the stream's end
-      process_pixel<M, S>(a, a.mode, base + threadIdx.x, lane, lds[wv]);
-    }
+    process_tile<M, S, BLOCK>(a, t0, tile_px, lane, lds[wv]);
   }
 }
 

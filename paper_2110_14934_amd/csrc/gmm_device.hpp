@@ -175,8 +175,14 @@ constexpr int kNV = static_cast<int>(value_count(M, C, sizeof(S)));
 // skips the other. A lane's offsets are a VGPR plus compile-time constants, so each state access
 // is one buffer instruction. The range checked by the hardware (num_records) is the whole block:
 // an access outside it reads 0 and drops its write instead of touching other memory. The host
-// keeps every block below 4 GiB.
+// keeps every block below 2 GiB, so that an offset of kNoAccess (plus a few bytes) is always
+// outside: a lane that must not touch memory issues the same instruction with that offset. Loads
+// and stores are thereby never skipped by a branch, and the compiler, which counts outstanding
+// memory instructions to place its waits (stores included, on this GPU), can count them exactly
+// and wait for just the loads a value comes from instead of for everything issued.
 constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family descriptor word 3
+constexpr uint32_t kNoAccess = 0x80000000u;
+__device__ __forceinline__ uint32_t at_if(bool on, uint32_t off) { return on ? off : kNoAccess; }
 constexpr uint32_t kMaxRows = 8;
 
 struct TileLayout {
@@ -283,8 +289,9 @@ __device__ __forceinline__ StateBlock make_block(void* base, uint32_t tiles64) {
 __device__ __forceinline__ float load_scale(const StateBlock& b, uint32_t p) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, b.scale + 4u * (p >> 6), 0, 0));
 }
-__device__ __forceinline__ void store_scale(float g, const StateBlock& b, uint32_t p) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, g), b.rsrc, b.scale + 4u * (p >> 6), 0, 0);
+__device__ __forceinline__ void store_scale(float g, const StateBlock& b, uint32_t p, bool on) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, g), b.rsrc, at_if(on, b.scale + 4u * (p >> 6)), 0,
+                                        0);
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -441,11 +448,11 @@ __device__ __forceinline__ float value_or_pad(const Mix<M, C>& m) {
 
 // Row c of pixel p into the Mix (values past the last one are padding and dropped).
 template <int M, int C, typename S, int c>
-__device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane) {
+__device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane, bool on) {
   constexpr int NV = kNV<M, C, S>, vpw = 4 / static_cast<int>(sizeof(S));
   constexpr uint32_t W = Plan<M, C, S>::L.width[c], off = Plan<M, C, S>::L.off[c];
   constexpr int v0 = static_cast<int>(Plan<M, C, S>::L.first[c]);
-  const RowWords<W> o = load_row<W>(b.rsrc, base + off + lane * W);
+  const RowWords<W> o = load_row<W>(b.rsrc, at_if(on, base + off + lane * W));
   static_for<0, static_cast<int>(W / sizeof(S))>([&](auto i_) RGBD_BODY {
     constexpr int i = RGBD_I(i_);
     if constexpr (v0 + i < NV) field<M, C, S, v0 + i>(m) = BufIO<S>::from_word(o.w[i / vpw], i % vpw);
@@ -454,7 +461,8 @@ __device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint
 
 // Row c of pixel p from the Mix.
 template <int M, int C, typename S, int c>
-__device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane) {
+__device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane,
+                                          bool on) {
   constexpr int vpw = 4 / static_cast<int>(sizeof(S));
   constexpr uint32_t W = Plan<M, C, S>::L.width[c], off = Plan<M, C, S>::L.off[c];
   constexpr int v0 = static_cast<int>(Plan<M, C, S>::L.first[c]);
@@ -463,14 +471,14 @@ __device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& 
     constexpr int k = RGBD_I(k_);
     o.w[k] = BufIO<S>::word(value_or_pad<M, C, S, v0 + k * vpw>(m), value_or_pad<M, C, S, v0 + k * vpw + vpw - 1>(m));
   });
-  store_row<W>(o, b.rsrc, base + off + lane * W);
+  store_row<W>(o, b.rsrc, at_if(on, base + off + lane * W));
 }
 
 // Values [0, LIMIT) of pixel p, straight into the Mix (see value_read for what comes along). A
 // value not read is left at 0 - a variance at 1, so that keys stay finite (any use of it is
-// discarded by the caller). LIMIT = NV reads everything.
+// discarded by the caller). LIMIT = NV reads everything. A lane with `on` false reads 0s.
 template <int M, int C, typename S, int LIMIT = kNV<M, C, S>>
-__device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+__device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on = true) {
   constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
@@ -482,10 +490,10 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
   });
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) read_row<M, C, S, c>(m, b, base, lane);
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) read_row<M, C, S, c>(m, b, base, lane, on);
   });
   if constexpr (LIMIT > nf && nw > 0) {
-    const uint32_t sbase = b.cold + p * P::sb;
+    const uint32_t sbase = at_if(on, b.cold + p * P::sb);
     // whole 16-byte groups of the suffix, then single words
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
@@ -510,9 +518,9 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
 
 // The values of pixel p that a load of [0, LF) did not bring: the rows from the first one
 // starting at or past LF, and the suffix unless that load read it. With load_mix<LF> before it,
-// the Mix holds the whole state.
+// the Mix holds the whole state. A lane with `on` false reads 0s.
 template <int M, int C, typename S, int LF>
-__device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+__device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on) {
   constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
@@ -520,10 +528,10 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= LF) read_row<M, C, S, c>(m, b, base, lane);
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= LF) read_row<M, C, S, c>(m, b, base, lane, on);
   });
   if constexpr (LF <= nf && nw > 0) {
-    const uint32_t sbase = b.cold + p * P::sb;
+    const uint32_t sbase = at_if(on, b.cold + p * P::sb);
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
       const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, sbase + 16u * g, 0, 0);
@@ -547,9 +555,10 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
 
 // Values [0, LIMIT) of pixel p from the Mix (whole rows and the whole suffix, as load_mix reads
 // them). ROWS / SUFFIX select the parts written, so that a caller can store the rows of every
-// lane with one instruction per row and the suffix of some lanes only.
+// lane with one instruction per row and the suffix of some lanes only. A lane with `on` false
+// writes nothing.
 template <int M, int C, typename S, int LIMIT = kNV<M, C, S>, bool ROWS = true, bool SUFFIX = true>
-__device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+__device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on) {
   constexpr int es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
@@ -557,10 +566,11 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (ROWS && static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) write_row<M, C, S, c>(m, b, base, lane);
+    if constexpr (ROWS && static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT)
+      write_row<M, C, S, c>(m, b, base, lane, on);
   });
   if constexpr (SUFFIX && LIMIT > nf && nw > 0) {
-    const uint32_t sbase = b.cold + p * P::sb;
+    const uint32_t sbase = at_if(on, b.cold + p * P::sb);
     static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
       constexpr int g = RGBD_I(g_);
       u32x4 w = {0u, 0u, 0u, 0u};
@@ -581,15 +591,15 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
 }
 
 // The rows of pixel p starting at or after value FROM, from the Mix: the rows a row store of
-// values [0, FROM) leaves out.
+// values [0, FROM) leaves out. A lane with `on` false writes nothing.
 template <int M, int C, typename S, int FROM>
-__device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateBlock& b, uint32_t p) {
+__device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on) {
   using P = Plan<M, C, S>;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= FROM) write_row<M, C, S, c>(m, b, base, lane);
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= FROM) write_row<M, C, S, c>(m, b, base, lane, on);
   });
 }
 
@@ -615,12 +625,13 @@ __host__ __device__ constexpr uint32_t suffix_rank_bytes(int r) {
 }
 
 // The suffix of pixel p from the Mix, piece by piece as store_mix cuts it (16-byte groups, then
-// words): every piece when `all`, else only the pieces holding a value of rank r. After a frame
-// in which the updated component kept its rank r, only the weights (in the hot rows) and rank
-// r changed: any other piece would rewrite the bits it holds, and each piece is one more write
-// request of a lane.
+// words): every piece when `all`, else only the pieces holding a value of rank r; nothing when
+// `on` is false. After a frame in which the updated component kept its rank r, only the weights
+// (in the hot rows) and rank r changed: any other piece would rewrite the bits it holds, and each
+// piece is one more write request of a lane.
 template <int M, int C, typename S>
-__device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool all, int r) {
+__device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on, bool all,
+                                                int r) {
   constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
   constexpr int nf = static_cast<int>(P::nf), nw = static_cast<int>(P::sb / 4);
@@ -634,23 +645,21 @@ __device__ __forceinline__ void store_suffix_of(const Mix<M, C>& m, const StateB
   static_for<0, nw / 4>([&](auto g_) RGBD_BODY {
     constexpr int g = RGBD_I(g_);
     constexpr int a = nf + 4 * g * vpw, e = nf + (4 * g + 4) * vpw;
-    if (all | ((lo < e) & (hi > a))) {
-      u32x4 w = {0u, 0u, 0u, 0u};
-      static_for<0, 4>([&](auto i_) RGBD_BODY {
-        constexpr int i = RGBD_I(i_);
-        constexpr int v = nf + (4 * g + i) * vpw;
-        w[i] = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
-      });
-      __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, sbase + 16u * g, 0, 0);
-    }
+    const bool put = on & (all | ((lo < e) & (hi > a)));
+    u32x4 w = {0u, 0u, 0u, 0u};
+    static_for<0, 4>([&](auto i_) RGBD_BODY {
+      constexpr int i = RGBD_I(i_);
+      constexpr int v = nf + (4 * g + i) * vpw;
+      w[i] = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+    });
+    __builtin_amdgcn_raw_buffer_store_b128(w, b.rsrc, at_if(put, sbase + 16u * g), 0, 0);
   });
   static_for<(nw / 4) * 4, nw>([&](auto w_) RGBD_BODY {
     constexpr int wi = RGBD_I(w_);
     constexpr int v = nf + wi * vpw;
-    if (all | ((lo < v + vpw) & (hi > v))) {
-      const uint32_t w = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
-      __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, sbase + 4u * wi, 0, 0);
-    }
+    const bool put = on & (all | ((lo < v + vpw) & (hi > v)));
+    const uint32_t w = BufIO<S>::word(sv(std::integral_constant<int, v>{}), sv(std::integral_constant<int, v + vpw - 1>{}));
+    __builtin_amdgcn_raw_buffer_store_b32(w, b.rsrc, at_if(put, sbase + 4u * wi), 0, 0);
   });
 }
 

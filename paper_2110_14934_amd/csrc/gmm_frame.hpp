@@ -76,7 +76,7 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
 // (direct weights), or rank 0 and rank 1's key (scaled), and in the scaled form the tile's scale.
 template <int M, int C, typename S>
 __device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid) {
-  if (valid) load_mix<M, C, S, kFastLoad<M, C, S>>(m, blk, p);
+  load_mix<M, C, S, kFastLoad<M, C, S>>(m, blk, p, valid);
   if constexpr (kScaled<S>) m.g = load_scale(blk, p);
 }
 
@@ -90,12 +90,55 @@ __device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk,
 // computes for such a pixel, so results never depend on which path ran. `valid` lanes hold a
 // pixel; `active` lanes update it (a depth hole is valid but not active: in the direct form it
 // writes back what it read; in the scaled form it rescales its weights to the tile's new scale,
-// hold_step). In the scaled form the tile's first lane then writes the new scale. Returns the
-// foreground bit; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
+// hold_step). In the scaled form the tile's first lane then writes the new scale.
+// In three parts, and every load and store is issued by every lane (a lane with nothing to move
+// uses an offset outside the block), so no branch hides a memory instruction from the count the
+// compiler keeps for its waits: step_begin runs fast_step and issues the loads of the rest of
+// the state (their results are used only by lanes that take the general path); step_compute
+// runs the general step on those lanes; step_store writes back. The caller issues the other
+// modality's step_begin before this one's step_store, so that a wait for one modality's loads
+// never waits for the other's stores.
 template <int M, int C, typename S>
-__device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
-                                              bool active, const float (&x)[C], const ModelConsts& k,
-                                              uint32_t& wave_bytes) {
+struct StepState {
+  Mix<M, C> full;  // the whole state as read (general-path lanes)
+  bool slow;       // this lane takes the general path
+  bool fg;         // its foreground bit
+  int kept;        // the rank its updated component kept, or -1 when the ranks were reordered
+};
+
+template <int M, int C, typename S>
+__device__ __forceinline__ void step_begin(Mix<M, C>& m, StepState<M, C, S>& st, const StateBlock& blk, uint32_t p,
+                                           bool valid, bool active, const float (&x)[C], const ModelConsts& k) {
+  constexpr bool SC = kScaled<S>;
+  st.full = m;  // the prefix as read (fast_step updates m in place)
+  const bool fast = active && fast_step<M, C, SC>(m, x, k);
+  st.slow = SC ? valid && !fast : active && !fast;
+  load_rest<M, C, S, kFastLoad<M, C, S>>(st.full, blk, p, st.slow);
+}
+
+template <int M, int C, typename S>
+__device__ __forceinline__ void step_compute(Mix<M, C>& m, StepState<M, C, S>& st, bool active, const float (&x)[C],
+                                             const ModelConsts& k) {
+  constexpr bool SC = kScaled<S>;
+  st.fg = false;
+  st.kept = -1;
+  if (st.slow) {  // no memory access in here
+    int j = M, q = M;
+    bool all = true;
+    if (SC && !active) {
+      if constexpr (SC) hold_step<M, C>(st.full, k);
+    } else {
+      st.fg = mix_step<M, C, SC>(st.full, x, k, j, q, all);
+    }
+    st.kept = !all && (j < M ? j : M - 1) == q ? q : -1;
+    m = st.full;
+  }
+}
+
+// The write-back; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
+template <int M, int C, typename S>
+__device__ __forceinline__ void step_store(const Mix<M, C>& m, const StepState<M, C, S>& st, const StateBlock& blk,
+                                           uint32_t p, bool valid, uint32_t& wave_bytes) {
   constexpr int NV = kNV<M, C, S>;
   constexpr int LF = kFastLoad<M, C, S>;
   constexpr int SF = kFastStore<M, C, S>;
@@ -103,23 +146,8 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   using P = Plan<M, C, S>;
   constexpr int NR = static_cast<int>(P::nf);  // values held by the hot rows
   constexpr bool SC = kScaled<S>;
-  bool fg = false;
-  const Mix<M, C> read = m;  // the prefix as read (fast_step updates m in place)
-  const bool fast = active && fast_step<M, C, SC>(m, x, k);
-  const bool slow = SC ? valid && !fast : active && !fast;
-  int kept = -1;  // the rank the updated component kept, or -1 when the ranks were reordered
-  if (slow) {  // m now holds each lane's own path's values
-    m = read;
-    load_rest<M, C, S, LF>(m, blk, p);
-    int j = M, q = M;
-    bool all = true;
-    if (SC && !active) {
-      if constexpr (SC) hold_step<M, C>(m, k);
-    } else {
-      fg = mix_step<M, C, SC>(m, x, k, j, q, all);
-    }
-    kept = !all && (j < M ? j : M - 1) == q ? q : -1;
-  }
+  const bool slow = st.slow;
+  const int kept = st.kept;
   // Write-back: every piece both paths write goes out in one store for all the lanes that write
   // it (a hot row then leaves the wave as one write, not as one per path). Both paths write the
   // rows the fast store covers; when the fast store reaches into the suffix (the rows cannot
@@ -127,13 +155,11 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   // otherwise the suffix, are the general path's alone; of the suffix, a lane whose updated
   // component kept its rank writes only the pieces holding that rank.
   constexpr bool kSuffixShared = SF > NR;
-  if (valid) store_mix<M, C, S, SF, true, kSuffixShared>(m, blk, p);
-  if (slow) {
-    if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF>(m, blk, p);
-    if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, kept < 0, kept);
-  }
+  store_mix<M, C, S, SF, true, kSuffixShared>(m, blk, p, valid);
+  if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF>(m, blk, p, slow);
+  if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, slow, kept < 0, kept);
   if constexpr (SC) {  // every valid lane holds the tile's new scale
-    if (valid && (p & 63u) == 0) store_scale(m.g, blk, p);
+    store_scale(m.g, blk, p, valid && (p & 63u) == 0);
     wave_bytes += 8u;
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
@@ -149,21 +175,33 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
       wave_bytes += __popcll(__ballot(slow && kept == r)) * suffix_rank_bytes<M, C, S>(r);
     });
   }
-  return fg;
+}
+
+// The three parts in one, for a single modality; returns the foreground bit.
+template <int M, int C, typename S>
+__device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
+                                              bool active, const float (&x)[C], const ModelConsts& k,
+                                              uint32_t& wave_bytes) {
+  StepState<M, C, S> st;
+  step_begin<M, C, S>(m, st, blk, p, valid, active, x, k);
+  step_compute<M, C, S>(m, st, active, x, k);
+  step_store<M, C, S>(m, st, blk, p, valid, wave_bytes);
+  return st.fg;
 }
 
 // Pixel p of stream `a` (p may lie past the end: such lanes only take part in the ballots).
-// `mode` must be uniform over the wave. AUG compiles the four-channel variant in (kModeAug):
+// MODE (a compile-time combination of kModeRGB, kModeDepth, kModeFuse, or kModeAug alone) selects
+// the steps, so that no branch on it stands between the memory instructions. kModeAug is the
+// four-channel variant:
 // one mixture over (R, G, B, D8) with D8 = min(255, depth >> 4), the augmentation the paper
 // describes and rejects in Sec. III.B; its mask goes to fg_rgb.
-template <int M, typename S, bool AUG = false>
-__device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint32_t p, int lane,
-                                              uint32_t* lds_wave) {
+template <int M, typename S, int MODE>
+__device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, int lane, uint32_t* lds_wave) {
   const uint32_t wave_base = p - lane;
   const bool valid = p < a.npix;
   bool fgc = false, fgd = false;
   uint32_t wave_bytes = 0;
-  if (AUG && (mode & kModeAug) != 0) {
+  if constexpr ((MODE & kModeAug) != 0) {
     const StateBlock blk = make_block<M, 4, S>(a.st_rgb, a.tiles64);
     Mix<M, 4> m;
     load_prefix<M, 4, S>(m, blk, p, valid);
@@ -176,7 +214,7 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
     const uint64_t bits = __ballot(fg);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
-  const bool do_c = (mode & kModeRGB) != 0, do_d = (mode & kModeDepth) != 0, do_f = (mode & kModeFuse) != 0;
+  constexpr bool do_c = (MODE & kModeRGB) != 0, do_d = (MODE & kModeDepth) != 0, do_f = (MODE & kModeFuse) != 0;
   const StateBlock blk_c = make_block<M, 3, S>(a.st_rgb, a.tiles64);
   const StateBlock blk_d = make_block<M, 1, S>(a.st_depth, a.tiles64);
   Mix<M, 3> mc;
@@ -196,30 +234,66 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, int mode, uint
   if (do_d) load_prefix<M, 1, S>(md, blk_d, pc, true);
   float x[3] = {0.f, 0.f, 0.f};
   if (do_c) finish_rgb_pixel(rl, lane, lds_wave, x);
-  if (do_c) {
-    fgc = step_modality<M, 3, S>(mc, blk_c, p, valid, valid, x, a.kc, wave_bytes);
-    const uint64_t bits = __ballot(fgc);
-    if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
+  const bool active_d = valid && !(a.kd.hole_skip && xd == 0.f);
+  const float x1[1] = {xd};
+  // colour computed before depth's loads go out, colour written back after them
+  StepState<M, 3, S> sc;
+  StepState<M, 1, S> sd;
+  if constexpr (do_c) {
+    step_begin<M, 3, S>(mc, sc, blk_c, p, valid, valid, x, a.kc);
+    step_compute<M, 3, S>(mc, sc, valid, x, a.kc);
+    fgc = sc.fg;
   }
-  if (do_d) {
-    const bool active = valid && !(a.kd.hole_skip && xd == 0.f);
-    const float x1[1] = {xd};
-    fgd = step_modality<M, 1, S>(md, blk_d, p, valid, active, x1, a.kd, wave_bytes);
-    const uint64_t bits = __ballot(fgd);
-    if (lane == 0 && valid) a.fg_depth[wave_base >> 6] = bits;
+  if constexpr (do_d) step_begin<M, 1, S>(md, sd, blk_d, p, valid, active_d, x1, a.kd);
+  if constexpr (do_c) step_store<M, 3, S>(mc, sc, blk_c, p, valid, wave_bytes);
+  if constexpr (do_d) {
+    step_compute<M, 1, S>(md, sd, active_d, x1, a.kd);
+    fgd = sd.fg;
+    step_store<M, 1, S>(md, sd, blk_d, p, valid, wave_bytes);
   }
-  if (do_f) {
-    bool fgf = false;
-    if (valid) {
-      const uint32_t st = fuse_transition(fst, fgc, fgd);
-      a.fstate[p] = static_cast<uint8_t>(st);
-      fgf = (st >> 3) & 1u;
-    }
-    const uint64_t bits = __ballot(fgf);
-    if (lane == 0 && valid) a.fused[wave_base >> 6] = bits;
+  // the List 1 step and the mask words last: their stores sit behind lane conditions
+  bool fgf = false;
+  if (do_f && valid) {
+    const uint32_t st = fuse_transition(fst, fgc, fgd);
+    a.fstate[p] = static_cast<uint8_t>(st);
+    fgf = (st >> 3) & 1u;
+  }
+  const uint64_t bc = __ballot(fgc), bd = __ballot(fgd), bf = __ballot(fgf);
+  if (lane == 0 && valid) {
+    if (do_c) a.fg_rgb[wave_base >> 6] = bc;
+    if (do_d) a.fg_depth[wave_base >> 6] = bd;
+    if (do_f) a.fused[wave_base >> 6] = bf;
   }
   // one wave owns each entry, and launches on a handle are ordered: a plain add is exact
   if (a.wave_bytes != nullptr && lane == 0 && valid) a.wave_bytes[wave_base >> 6] += wave_bytes;
+}
+
+// Pixels [t0, t0 + tile_px) of stream `a` (tile_px a multiple of BLOCK; the part past the
+// stream's end is skipped), BLOCK at a time, the stream's mode resolved once for the tile.
+template <int M, typename S, int MODE, int BLOCK>
+__device__ __forceinline__ void process_tile_mode(const FrameArgs& a, uint32_t t0, uint32_t tile_px, int lane,
+                                                  uint32_t* lds_wave) {
+  for (uint32_t sub = 0; sub < tile_px; sub += BLOCK) {
+    const uint32_t base = t0 + sub;
+    if (base >= a.npix) break;  // uniform: the rest of the tile is past the stream's end
+    process_pixel<M, S, MODE>(a, base + threadIdx.x, lane, lds_wave);
+  }
+}
+
+template <int M, typename S, int BLOCK>
+__device__ __forceinline__ void process_tile(const FrameArgs& a, uint32_t t0, uint32_t tile_px, int lane,
+                                             uint32_t* lds_wave) {
+  switch (a.mode) {  // the modes a batch accepts
+    case kModeRGB | kModeDepth | kModeFuse:
+      process_tile_mode<M, S, kModeRGB | kModeDepth | kModeFuse, BLOCK>(a, t0, tile_px, lane, lds_wave);
+      break;
+    case kModeRGB | kModeDepth:
+      process_tile_mode<M, S, kModeRGB | kModeDepth, BLOCK>(a, t0, tile_px, lane, lds_wave);
+      break;
+    case kModeRGB: process_tile_mode<M, S, kModeRGB, BLOCK>(a, t0, tile_px, lane, lds_wave); break;
+    case kModeDepth: process_tile_mode<M, S, kModeDepth, BLOCK>(a, t0, tile_px, lane, lds_wave); break;
+    default: break;
+  }
 }
 
 }  // namespace rgbd

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
   __shared__ uint32_t lds[kWavesPerBlock][48];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  process_pixel<M, S, (MODE & kModeAug) != 0>(a, MODE, blockIdx.x * kBlock + threadIdx.x, lane, lds[wv]);
+  process_pixel<M, S, MODE>(a, blockIdx.x * kBlock + threadIdx.x, lane, lds[wv]);
 }
 
 // Standalone List 1 over two given masks.

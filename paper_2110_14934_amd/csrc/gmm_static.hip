@@ -67,11 +67,7 @@ __global__ void __launch_bounds__(BLOCK) batch_search_kernel(const FrameArgs* __
     }
     const FrameArgs a = table[lo];
     const uint32_t t0 = (t - first[lo]) * tile_px;
-    for (uint32_t sub = 0; sub < tile_px; sub += BLOCK) {
-      const uint32_t base = t0 + sub;
-      if (base >= a.npix) break;  // uniform: the rest of the tile is past the stream's end
-      process_pixel<M, S>(a, a.mode, base + threadIdx.x, lane, lds[wv]);
-    }
+    process_tile<M, S, BLOCK>(a, t0, tile_px, lane, lds[wv]);
   }
 }
 

@@ -66,6 +66,16 @@ def test_create_rejects_bad_config_without_device(lib, field, value, needle):
     assert needle in str(e.value)
 
 
+def test_state_above_2_gib_per_modality_is_rejected_without_device(lib):
+    # fp32, M = 5: 104 bytes of colour state per pixel, so 4608 x 4608 (2.2 GB) is too large, and
+    # depth alone (64 bytes per pixel, 1.36 GB) fits
+    cfg = _abi.gmm_config_default(4608, 4608, _abi.GMM_RGB, 5)
+    with pytest.raises(_abi.GmmError) as e:
+        _abi.gmm_exec_stream_bytes(cfg)
+    assert e.value.status == _abi.GMM_ERR_INVALID_ARG and "2 GiB" in str(e.value)
+    assert _abi.gmm_exec_stream_bytes(_abi.gmm_config_default(4608, 4608, _abi.GMM_DEPTH, 5)) > 64 * 4608 * 4608
+
+
 def test_create_rejects_bad_sigma_and_floor(lib):
     cfg = _abi.gmm_config_default(64, 48, 3, 3)
     cfg.var_min[1] = 2501.0   # above sigma0^2 of depth
