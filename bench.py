@@ -761,7 +761,10 @@ def bench_plain(args) -> int:
                    "launch": args.mode, "rho": args.rho, "variant": args.variant},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"rgbd::frame_kernel<5, float, {8 if augmented else 7}>",
+                     # the single-stream kernel streams its rows and frames (cache policy 2) for
+                     # a state of 128 MiB or more, else keeps the default policy (0)
+                     "kernel": f"rgbd::frame_kernel<5, float, {8 if augmented else 7}, "
+                               f"{2 if seg.state_bytes() >= 128 << 20 else 0}>",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "full_rewrite_bytes_per_launch": None if augmented else sorted_bytes,
                      "full_rewrite_frac": None if augmented else sorted_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,

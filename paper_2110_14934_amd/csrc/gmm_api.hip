@@ -399,7 +399,7 @@ gmm_status gmm_apply_frame(gmm_handle* h, const uint8_t* rgb, int64_t rgb_pitch_
   const FrameArgs a = frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth, nullptr);
   const int mode = (has_rgb(h) ? kModeRGB : 0) | (has_depth(h) ? kModeDepth : 0);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, mode, s);
+  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, mode, streams_state(h), s);
   if (e != hipSuccess) return hip_fail(e, "frame kernel launch");
   h->last_stream = s;
   return GMM_OK;
@@ -436,7 +436,7 @@ gmm_status gmm_apply_frame_fused(gmm_handle* h, const uint8_t* rgb, int64_t rgb_
   if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
   const FrameArgs a = frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg_rgb, fg_depth, fused);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeRGB | kModeDepth | kModeFuse, s);
+  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeRGB | kModeDepth | kModeFuse, streams_state(h), s);
   if (e != hipSuccess) return hip_fail(e, "fused frame kernel launch");
   h->last_stream = s;
   return GMM_OK;
@@ -458,7 +458,7 @@ gmm_status gmm_apply_frame_augmented(gmm_handle* h, const uint8_t* rgb, int64_t 
   if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");
   const FrameArgs a = frame_args(h, rgb, rgb_pitch_bytes, depth, depth_pitch_bytes, fg, nullptr, nullptr);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeAug, s);
+  hipError_t e = launch_frame(a, h->cfg.M, h->cfg.state_dtype, kModeAug, streams_state(h), s);
   if (e != hipSuccess) return hip_fail(e, "augmented frame kernel launch");
   h->last_stream = s;
   return GMM_OK;

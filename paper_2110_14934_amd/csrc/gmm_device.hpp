@@ -297,43 +297,51 @@ __device__ __forceinline__ void store_scale(float g, const StateBlock& b, uint32
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
+// Cache policy of the hot rows' loads and stores (the buffer instructions' cache-policy operand).
+// kStream marks them non-temporal: a frame streams through every row once, and a state far
+// larger than the caches would otherwise evict from them the lines that the general path's
+// scattered suffix accesses and the frames could still hit. A state that fits in the last-level
+// cache keeps the default policy, so that it stays there from frame to frame.
+constexpr int kCached = 0;
+constexpr int kStream = 2;  // nt
+
 // One lane's words of a row (W bytes), moved by one buffer instruction of that width.
 template <uint32_t W>
 struct RowWords {
   uint32_t w[W / 4];
 };
 
-template <uint32_t W>
+template <uint32_t W, int CP>
 __device__ __forceinline__ RowWords<W> load_row(const __amdgpu_buffer_rsrc_t& r, uint32_t off) {
   RowWords<W> o{};
   if constexpr (W == 16) {
-    const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP);
     o.w[0] = x[0];
     o.w[1] = x[1];
     o.w[2] = x[2];
     o.w[3] = x[3];
   } else if constexpr (W == 8) {
-    const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP);
     o.w[0] = x[0];
     o.w[1] = x[1];
   } else {
     static_assert(W == 4, "rows are 16, 8 or 4 bytes per lane");
-    o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, CP);
   }
   return o;
 }
 
-template <uint32_t W>
+template <uint32_t W, int CP>
 __device__ __forceinline__ void store_row(const RowWords<W>& o, const __amdgpu_buffer_rsrc_t& r, uint32_t off) {
   if constexpr (W == 16) {
     const u32x4 x = {o.w[0], o.w[1], o.w[2], o.w[3]};
-    __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, CP);
   } else if constexpr (W == 8) {
     const u32x2 x = {o.w[0], o.w[1]};
-    __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, CP);
   } else {
     static_assert(W == 4, "rows are 16, 8 or 4 bytes per lane");
-    __builtin_amdgcn_raw_buffer_store_b32(o.w[0], r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(o.w[0], r, off, 0, CP);
   }
 }
 
@@ -447,12 +455,12 @@ __device__ __forceinline__ float value_or_pad(const Mix<M, C>& m) {
 }
 
 // Row c of pixel p into the Mix (values past the last one are padding and dropped).
-template <int M, int C, typename S, int c>
+template <int M, int C, typename S, int c, int CP>
 __device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane, bool on) {
   constexpr int NV = kNV<M, C, S>, vpw = 4 / static_cast<int>(sizeof(S));
   constexpr uint32_t W = Plan<M, C, S>::L.width[c], off = Plan<M, C, S>::L.off[c];
   constexpr int v0 = static_cast<int>(Plan<M, C, S>::L.first[c]);
-  const RowWords<W> o = load_row<W>(b.rsrc, at_if(on, base + off + lane * W));
+  const RowWords<W> o = load_row<W, CP>(b.rsrc, at_if(on, base + off + lane * W));
   static_for<0, static_cast<int>(W / sizeof(S))>([&](auto i_) RGBD_BODY {
     constexpr int i = RGBD_I(i_);
     if constexpr (v0 + i < NV) field<M, C, S, v0 + i>(m) = BufIO<S>::from_word(o.w[i / vpw], i % vpw);
@@ -460,7 +468,7 @@ __device__ __forceinline__ void read_row(Mix<M, C>& m, const StateBlock& b, uint
 }
 
 // Row c of pixel p from the Mix.
-template <int M, int C, typename S, int c>
+template <int M, int C, typename S, int c, int CP>
 __device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& b, uint32_t base, uint32_t lane,
                                           bool on) {
   constexpr int vpw = 4 / static_cast<int>(sizeof(S));
@@ -471,13 +479,13 @@ __device__ __forceinline__ void write_row(const Mix<M, C>& m, const StateBlock& 
     constexpr int k = RGBD_I(k_);
     o.w[k] = BufIO<S>::word(value_or_pad<M, C, S, v0 + k * vpw>(m), value_or_pad<M, C, S, v0 + k * vpw + vpw - 1>(m));
   });
-  store_row<W>(o, b.rsrc, at_if(on, base + off + lane * W));
+  store_row<W, CP>(o, b.rsrc, at_if(on, base + off + lane * W));
 }
 
 // Values [0, LIMIT) of pixel p, straight into the Mix (see value_read for what comes along). A
 // value not read is left at 0 - a variance at 1, so that keys stay finite (any use of it is
 // discarded by the caller). LIMIT = NV reads everything. A lane with `on` false reads 0s.
-template <int M, int C, typename S, int LIMIT = kNV<M, C, S>>
+template <int M, int C, typename S, int LIMIT = kNV<M, C, S>, int CP = kCached>
 __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on = true) {
   constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
@@ -490,7 +498,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
   });
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) read_row<M, C, S, c>(m, b, base, lane, on);
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT) read_row<M, C, S, c, CP>(m, b, base, lane, on);
   });
   if constexpr (LIMIT > nf && nw > 0) {
     const uint32_t sbase = at_if(on, b.cold + p * P::sb);
@@ -519,7 +527,7 @@ __device__ __forceinline__ void load_mix(Mix<M, C>& m, const StateBlock& b, uint
 // The values of pixel p that a load of [0, LF) did not bring: the rows from the first one
 // starting at or past LF, and the suffix unless that load read it. With load_mix<LF> before it,
 // the Mix holds the whole state. A lane with `on` false reads 0s.
-template <int M, int C, typename S, int LF>
+template <int M, int C, typename S, int LF, int CP = kCached>
 __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on) {
   constexpr int NV = kNV<M, C, S>, es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
@@ -528,7 +536,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= LF) read_row<M, C, S, c>(m, b, base, lane, on);
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= LF) read_row<M, C, S, c, CP>(m, b, base, lane, on);
   });
   if constexpr (LF <= nf && nw > 0) {
     const uint32_t sbase = at_if(on, b.cold + p * P::sb);
@@ -557,7 +565,7 @@ __device__ __forceinline__ void load_rest(Mix<M, C>& m, const StateBlock& b, uin
 // them). ROWS / SUFFIX select the parts written, so that a caller can store the rows of every
 // lane with one instruction per row and the suffix of some lanes only. A lane with `on` false
 // writes nothing.
-template <int M, int C, typename S, int LIMIT = kNV<M, C, S>, bool ROWS = true, bool SUFFIX = true>
+template <int M, int C, typename S, int LIMIT = kNV<M, C, S>, bool ROWS = true, bool SUFFIX = true, int CP = kCached>
 __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on) {
   constexpr int es = sizeof(S), vpw = 4 / es;
   using P = Plan<M, C, S>;
@@ -567,7 +575,7 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
     if constexpr (ROWS && static_cast<int>(Plan<M, C, S>::L.first[c]) < LIMIT)
-      write_row<M, C, S, c>(m, b, base, lane, on);
+      write_row<M, C, S, c, CP>(m, b, base, lane, on);
   });
   if constexpr (SUFFIX && LIMIT > nf && nw > 0) {
     const uint32_t sbase = at_if(on, b.cold + p * P::sb);
@@ -592,14 +600,14 @@ __device__ __forceinline__ void store_mix(const Mix<M, C>& m, const StateBlock& 
 
 // The rows of pixel p starting at or after value FROM, from the Mix: the rows a row store of
 // values [0, FROM) leaves out. A lane with `on` false writes nothing.
-template <int M, int C, typename S, int FROM>
+template <int M, int C, typename S, int FROM, int CP = kCached>
 __device__ __forceinline__ void store_rows_from(const Mix<M, C>& m, const StateBlock& b, uint32_t p, bool on) {
   using P = Plan<M, C, S>;
   const uint32_t lane = p & 63u;
   const uint32_t base = (p >> 6) * b.tile_rows;
   static_for<0, static_cast<int>(P::nrows)>([&](auto c_) RGBD_BODY {
     constexpr int c = RGBD_I(c_);
-    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= FROM) write_row<M, C, S, c>(m, b, base, lane, on);
+    if constexpr (static_cast<int>(Plan<M, C, S>::L.first[c]) >= FROM) write_row<M, C, S, c, CP>(m, b, base, lane, on);
   });
 }
 

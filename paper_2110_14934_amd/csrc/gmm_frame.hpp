@@ -21,12 +21,14 @@ struct RgbLoad {
   uint32_t b0, b1, b2;  // per lane: the pixel's bytes
 };
 
+template <int CP = kCached>
 __device__ __forceinline__ RgbLoad issue_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base, int lane) {
   RgbLoad r{};
   r.staged = a.rgb_dense && (wave_base + kWave <= a.npix);
   if (r.staged) {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.rgb + 3 * static_cast<uint64_t>(wave_base));
-    r.w = src[lane < 48 ? lane : 47];
+    if constexpr (CP == kStream) r.w = __builtin_nontemporal_load(&src[lane < 48 ? lane : 47]);
+    else r.w = src[lane < 48 ? lane : 47];
   } else {
     const uint32_t y = p / static_cast<uint32_t>(a.width);
     const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
@@ -55,15 +57,20 @@ __device__ __forceinline__ void finish_rgb_pixel(const RgbLoad& r, int lane, uin
 }
 
 // Colour pixel p, both halves at once (the four-channel path); lanes past the end read zeros.
+template <int CP = kCached>
 __device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base, int lane,
                                                uint32_t* lds_wave, bool valid, float (&x)[3]) {
-  const RgbLoad r = issue_rgb_pixel(a, valid ? p : a.npix - 1, wave_base, lane);
+  const RgbLoad r = issue_rgb_pixel<CP>(a, valid ? p : a.npix - 1, wave_base, lane);
   finish_rgb_pixel(r, lane, lds_wave, x);
   if (!valid) x[0] = x[1] = x[2] = 0.f;
 }
 
+template <int CP = kCached>
 __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p) {
-  if (a.depth_dense) return static_cast<float>(a.depth[p]);
+  if (a.depth_dense) {
+    if constexpr (CP == kStream) return static_cast<float>(__builtin_nontemporal_load(&a.depth[p]));
+    else return static_cast<float>(a.depth[p]);
+  }
   const uint32_t y = p / static_cast<uint32_t>(a.width);
   const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
   const uint16_t* row = reinterpret_cast<const uint16_t*>(
@@ -74,9 +81,9 @@ __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p
 // The values a frame needs when the pixel matches its rank-0 component and that component keeps
 // its rank (the fast-path prefix, in the hot rows): all weights, rank 0 and rank 1's variance
 // (direct weights), or rank 0 and rank 1's key (scaled), and in the scaled form the tile's scale.
-template <int M, int C, typename S>
+template <int M, int C, typename S, int CP = kCached>
 __device__ __forceinline__ void load_prefix(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid) {
-  load_mix<M, C, S, kFastLoad<M, C, S>>(m, blk, p, valid);
+  load_mix<M, C, S, kFastLoad<M, C, S>, CP>(m, blk, p, valid);
   if constexpr (kScaled<S>) m.g = load_scale(blk, p);
 }
 
@@ -106,14 +113,14 @@ struct StepState {
   int kept;        // the rank its updated component kept, or -1 when the ranks were reordered
 };
 
-template <int M, int C, typename S>
+template <int M, int C, typename S, int CP = kCached>
 __device__ __forceinline__ void step_begin(Mix<M, C>& m, StepState<M, C, S>& st, const StateBlock& blk, uint32_t p,
                                            bool valid, bool active, const float (&x)[C], const ModelConsts& k) {
   constexpr bool SC = kScaled<S>;
   st.full = m;  // the prefix as read (fast_step updates m in place)
   const bool fast = active && fast_step<M, C, SC>(m, x, k);
   st.slow = SC ? valid && !fast : active && !fast;
-  load_rest<M, C, S, kFastLoad<M, C, S>>(st.full, blk, p, st.slow);
+  load_rest<M, C, S, kFastLoad<M, C, S>, CP>(st.full, blk, p, st.slow);
 }
 
 template <int M, int C, typename S>
@@ -136,7 +143,7 @@ __device__ __forceinline__ void step_compute(Mix<M, C>& m, StepState<M, C, S>& s
 }
 
 // The write-back; adds the state bytes the wave's lanes read and wrote to `wave_bytes`.
-template <int M, int C, typename S>
+template <int M, int C, typename S, int CP = kCached>
 __device__ __forceinline__ void step_store(const Mix<M, C>& m, const StepState<M, C, S>& st, const StateBlock& blk,
                                            uint32_t p, bool valid, uint32_t& wave_bytes) {
   constexpr int NV = kNV<M, C, S>;
@@ -155,8 +162,8 @@ __device__ __forceinline__ void step_store(const Mix<M, C>& m, const StepState<M
   // otherwise the suffix, are the general path's alone; of the suffix, a lane whose updated
   // component kept its rank writes only the pieces holding that rank.
   constexpr bool kSuffixShared = SF > NR;
-  store_mix<M, C, S, SF, true, kSuffixShared>(m, blk, p, valid);
-  if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF>(m, blk, p, slow);
+  store_mix<M, C, S, SF, true, kSuffixShared, CP>(m, blk, p, valid);
+  if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF, CP>(m, blk, p, slow);
   if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, slow, kept < 0, kept);
   if constexpr (SC) {  // every valid lane holds the tile's new scale
     store_scale(m.g, blk, p, valid && (p & 63u) == 0);
@@ -178,14 +185,14 @@ __device__ __forceinline__ void step_store(const Mix<M, C>& m, const StepState<M
 }
 
 // The three parts in one, for a single modality; returns the foreground bit.
-template <int M, int C, typename S>
+template <int M, int C, typename S, int CP = kCached>
 __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& blk, uint32_t p, bool valid,
                                               bool active, const float (&x)[C], const ModelConsts& k,
                                               uint32_t& wave_bytes) {
   StepState<M, C, S> st;
-  step_begin<M, C, S>(m, st, blk, p, valid, active, x, k);
+  step_begin<M, C, S, CP>(m, st, blk, p, valid, active, x, k);
   step_compute<M, C, S>(m, st, active, x, k);
-  step_store<M, C, S>(m, st, blk, p, valid, wave_bytes);
+  step_store<M, C, S, CP>(m, st, blk, p, valid, wave_bytes);
   return st.fg;
 }
 
@@ -195,7 +202,7 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
 // four-channel variant:
 // one mixture over (R, G, B, D8) with D8 = min(255, depth >> 4), the augmentation the paper
 // describes and rejects in Sec. III.B; its mask goes to fg_rgb.
-template <int M, typename S, int MODE>
+template <int M, typename S, int MODE, int CP>
 __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, int lane, uint32_t* lds_wave) {
   const uint32_t wave_base = p - lane;
   const bool valid = p < a.npix;
@@ -204,13 +211,13 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   if constexpr ((MODE & kModeAug) != 0) {
     const StateBlock blk = make_block<M, 4, S>(a.st_rgb, a.tiles64);
     Mix<M, 4> m;
-    load_prefix<M, 4, S>(m, blk, p, valid);
-    const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel(a, p)) : 0u;
+    load_prefix<M, 4, S, CP>(m, blk, p, valid);
+    const uint32_t d = valid ? static_cast<uint32_t>(load_depth_pixel<CP>(a, p)) : 0u;
     float x3[3];
-    load_rgb_pixel(a, p, wave_base, lane, lds_wave, valid, x3);
+    load_rgb_pixel<CP>(a, p, wave_base, lane, lds_wave, valid, x3);
     const bool active = valid && !(a.kc.hole_skip && d == 0u);
     const float x[4] = {x3[0], x3[1], x3[2], static_cast<float>(min(d >> 4, 255u))};
-    const bool fg = step_modality<M, 4, S>(m, blk, p, valid, active, x, a.kc, wave_bytes);
+    const bool fg = step_modality<M, 4, S, CP>(m, blk, p, valid, active, x, a.kc, wave_bytes);
     const uint64_t bits = __ballot(fg);
     if (lane == 0 && valid) a.fg_rgb[wave_base >> 6] = bits;
   }
@@ -227,11 +234,11 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   // once, covers only them while the state prefixes stay in flight.
   const uint32_t pc = valid ? p : a.npix - 1;
   RgbLoad rl{};
-  if (do_c) rl = issue_rgb_pixel(a, pc, wave_base, lane);
-  const float xd = do_d ? load_depth_pixel(a, pc) : 0.f;
+  if (do_c) rl = issue_rgb_pixel<CP>(a, pc, wave_base, lane);
+  const float xd = do_d ? load_depth_pixel<CP>(a, pc) : 0.f;
   const uint32_t fst = do_f ? a.fstate[pc] : 0u;
-  if (do_c) load_prefix<M, 3, S>(mc, blk_c, pc, true);
-  if (do_d) load_prefix<M, 1, S>(md, blk_d, pc, true);
+  if (do_c) load_prefix<M, 3, S, CP>(mc, blk_c, pc, true);
+  if (do_d) load_prefix<M, 1, S, CP>(md, blk_d, pc, true);
   float x[3] = {0.f, 0.f, 0.f};
   if (do_c) finish_rgb_pixel(rl, lane, lds_wave, x);
   const bool active_d = valid && !(a.kd.hole_skip && xd == 0.f);
@@ -240,16 +247,16 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   StepState<M, 3, S> sc;
   StepState<M, 1, S> sd;
   if constexpr (do_c) {
-    step_begin<M, 3, S>(mc, sc, blk_c, p, valid, valid, x, a.kc);
+    step_begin<M, 3, S, CP>(mc, sc, blk_c, p, valid, valid, x, a.kc);
     step_compute<M, 3, S>(mc, sc, valid, x, a.kc);
     fgc = sc.fg;
   }
-  if constexpr (do_d) step_begin<M, 1, S>(md, sd, blk_d, p, valid, active_d, x1, a.kd);
-  if constexpr (do_c) step_store<M, 3, S>(mc, sc, blk_c, p, valid, wave_bytes);
+  if constexpr (do_d) step_begin<M, 1, S, CP>(md, sd, blk_d, p, valid, active_d, x1, a.kd);
+  if constexpr (do_c) step_store<M, 3, S, CP>(mc, sc, blk_c, p, valid, wave_bytes);
   if constexpr (do_d) {
     step_compute<M, 1, S>(md, sd, active_d, x1, a.kd);
     fgd = sd.fg;
-    step_store<M, 1, S>(md, sd, blk_d, p, valid, wave_bytes);
+    step_store<M, 1, S, CP>(md, sd, blk_d, p, valid, wave_bytes);
   }
   // the List 1 step and the mask words last: their stores sit behind lane conditions
   bool fgf = false;
@@ -269,14 +276,16 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
 }
 
 // Pixels [t0, t0 + tile_px) of stream `a` (tile_px a multiple of BLOCK; the part past the
-// stream's end is skipped), BLOCK at a time, the stream's mode resolved once for the tile.
+// stream's end is skipped), BLOCK at a time, the stream's mode resolved once for the tile. A
+// batched launch serves many streams, whose state together far exceeds the caches: its rows and
+// frames stream (kStream).
 template <int M, typename S, int MODE, int BLOCK>
 __device__ __forceinline__ void process_tile_mode(const FrameArgs& a, uint32_t t0, uint32_t tile_px, int lane,
                                                   uint32_t* lds_wave) {
   for (uint32_t sub = 0; sub < tile_px; sub += BLOCK) {
     const uint32_t base = t0 + sub;
     if (base >= a.npix) break;  // uniform: the rest of the tile is past the stream's end
-    process_pixel<M, S, MODE>(a, base + threadIdx.x, lane, lds_wave);
+    process_pixel<M, S, MODE, kStream>(a, base + threadIdx.x, lane, lds_wave);
   }
 }
 

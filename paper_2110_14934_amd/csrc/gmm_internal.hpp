@@ -40,7 +40,10 @@ struct FrameArgs {
 enum FrameMode : int { kModeRGB = 1, kModeDepth = 2, kModeFuse = 4, kModeAug = 8 };
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStream_t s);
+// `stream`: the kernel's rows and frames take the non-temporal cache policy (kStream), for a state
+// too large to stay in the last-level cache between frames (streams_state).
+hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, bool stream, hipStream_t s);
+constexpr size_t kStreamStateBytes = size_t(128) << 20;  // half the 256 MB last-level cache
 hipError_t launch_fuse(const uint64_t* fr, const uint64_t* fd, uint64_t* out, uint8_t* fstate,
                        int64_t npix, hipStream_t s);
 hipError_t launch_init(void* st, int dtype, uint32_t tiles64, int M, int C, float var0, hipStream_t s);
@@ -120,4 +123,6 @@ void place_state(gmm_handle* h, void* mem);
 // Enqueue the initial (all components empty) state on `s`.
 hipError_t init_state(gmm_handle* h, hipStream_t s);
 size_t state_bytes(const gmm_handle* h);
+// Whether a single-stream launch streams its state (at least kStreamStateBytes of it).
+inline bool streams_state(const gmm_handle* h) { return state_bytes(h) >= kStreamStateBytes; }
 }  // namespace rgbd

@@ -18,12 +18,12 @@ namespace rgbd {
 
 // One stream, one frame. MODE is a combination of kModeRGB, kModeDepth, kModeFuse, or kModeAug
 // alone (the four-channel variant).
-template <int M, typename S, int MODE>
+template <int M, typename S, int MODE, int CP>
 __global__ void __launch_bounds__(kBlock) frame_kernel(FrameArgs a) {
   __shared__ uint32_t lds[kWavesPerBlock][48];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  process_pixel<M, S, MODE>(a, blockIdx.x * kBlock + threadIdx.x, lane, lds[wv]);
+  process_pixel<M, S, MODE, CP>(a, blockIdx.x * kBlock + threadIdx.x, lane, lds[wv]);
 }
 
 // Standalone List 1 over two given masks.
@@ -105,30 +105,35 @@ static inline dim3 grid_for(int64_t n) {
   return dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock));
 }
 
-template <int M, typename S>
-static hipError_t launch_frame_ms(const FrameArgs& a, int mode, hipStream_t s) {
+template <int M, typename S, int CP>
+static hipError_t launch_frame_msc(const FrameArgs& a, int mode, hipStream_t s) {
   const dim3 g = grid_for(a.npix), b(kBlock);
   switch (mode) {
-    case kModeRGB: frame_kernel<M, S, kModeRGB><<<g, b, 0, s>>>(a); break;
-    case kModeDepth: frame_kernel<M, S, kModeDepth><<<g, b, 0, s>>>(a); break;
-    case kModeRGB | kModeDepth: frame_kernel<M, S, kModeRGB | kModeDepth><<<g, b, 0, s>>>(a); break;
+    case kModeRGB: frame_kernel<M, S, kModeRGB, CP><<<g, b, 0, s>>>(a); break;
+    case kModeDepth: frame_kernel<M, S, kModeDepth, CP><<<g, b, 0, s>>>(a); break;
+    case kModeRGB | kModeDepth: frame_kernel<M, S, kModeRGB | kModeDepth, CP><<<g, b, 0, s>>>(a); break;
     case kModeRGB | kModeDepth | kModeFuse:
-      frame_kernel<M, S, kModeRGB | kModeDepth | kModeFuse><<<g, b, 0, s>>>(a);
+      frame_kernel<M, S, kModeRGB | kModeDepth | kModeFuse, CP><<<g, b, 0, s>>>(a);
       break;
-    case kModeAug: frame_kernel<M, S, kModeAug><<<g, b, 0, s>>>(a); break;
+    case kModeAug: frame_kernel<M, S, kModeAug, CP><<<g, b, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int M, typename S>
+static hipError_t launch_frame_ms(const FrameArgs& a, int mode, bool stream, hipStream_t s) {
+  return stream ? launch_frame_msc<M, S, kStream>(a, mode, s) : launch_frame_msc<M, S, kCached>(a, mode, s);
+}
+
 template <typename S>
-static hipError_t launch_frame_s(const FrameArgs& a, int M, int mode, hipStream_t s) {
+static hipError_t launch_frame_s(const FrameArgs& a, int M, int mode, bool stream, hipStream_t s) {
   switch (M) {
-    case 1: return launch_frame_ms<1, S>(a, mode, s);
-    case 2: return launch_frame_ms<2, S>(a, mode, s);
-    case 3: return launch_frame_ms<3, S>(a, mode, s);
-    case 4: return launch_frame_ms<4, S>(a, mode, s);
-    case 5: return launch_frame_ms<5, S>(a, mode, s);
+    case 1: return launch_frame_ms<1, S>(a, mode, stream, s);
+    case 2: return launch_frame_ms<2, S>(a, mode, stream, s);
+    case 3: return launch_frame_ms<3, S>(a, mode, stream, s);
+    case 4: return launch_frame_ms<4, S>(a, mode, stream, s);
+    case 5: return launch_frame_ms<5, S>(a, mode, stream, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -137,11 +142,11 @@ bool frame_variant_compiled(int M, int dtype) {
   return M >= 1 && M <= 5 && (dtype == GMM_F32 || dtype == GMM_F16 || dtype == GMM_BF16);
 }
 
-hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, hipStream_t s) {
+hipError_t launch_frame(const FrameArgs& a, int M, int dtype, int mode, bool stream, hipStream_t s) {
   switch (dtype) {
-    case GMM_F32: return launch_frame_s<float>(a, M, mode, s);
-    case GMM_F16: return launch_frame_s<f16s>(a, M, mode, s);
-    case GMM_BF16: return launch_frame_s<bf16s>(a, M, mode, s);
+    case GMM_F32: return launch_frame_s<float>(a, M, mode, stream, s);
+    case GMM_F16: return launch_frame_s<f16s>(a, M, mode, stream, s);
+    case GMM_BF16: return launch_frame_s<bf16s>(a, M, mode, stream, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -92,6 +92,30 @@ def test_batch_bit_identical_to_single_streams(dtype, rho):
             s.close()
 
 
+def test_large_single_stream_bit_identical_to_batch():
+    """A stream whose state exceeds 128 MiB takes the single-stream kernel built for streaming
+    (non-temporal rows and frames, the batched kernels' policy); it must stay bit-identical to the
+    batched launch, masks every frame and the whole state at the end."""
+    spec = StreamSpec(1024, 800, n_boxes=2, box_min=40, box_max=120, hole_p=0.05, seed=17, index=0)
+    st = Stream(spec)
+    single = Segmenter(spec.width, spec.height, mods(spec), MIX.M, **kwargs(MIX))
+    batched = Segmenter(spec.width, spec.height, mods(spec), MIX.M, **kwargs(MIX))
+    batch = Batch([batched])
+    try:
+        assert single.state_bytes() >= 128 << 20
+        for t in range(6):
+            frames = _frames([st], t)
+            _single_step(single, *frames[0])
+            batch.apply(frames)
+            torch.cuda.synchronize()
+            _compare_bitwise([single], [batched], t)
+        assert np.array_equal(single.read_state(), batched.read_state())
+    finally:
+        batch.close()
+        single.close()
+        batched.close()
+
+
 def test_autotune_leaves_state_untouched_and_picks_a_candidate():
     streams = [Stream(s) for s in SPECS]
     segs = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
