@@ -118,16 +118,20 @@ def stream_bytes(spec, holes: float, M: int, esize: int, fused: bool) -> float:
     return b
 
 
-def io_bytes_per_frame(npix: int, rgb: bool = True, depth: bool = True, fused: bool = True) -> float:
+def io_bytes_per_frame(npix: int, rgb: bool = True, depth: bool = True, fused: bool = True,
+                       scaled: bool = True) -> float:
     """Bytes besides the mixture state: input pixels (3 B colour, 2 B depth), one mask bit per
-    modality, and for fusion the state byte read and written plus the fused bit."""
+    modality, the pixel's flags byte read and written (List 1 state with fusion; with fp32 state
+    (scaled weights) also the depth hole count), and the fused bit."""
     b = 0.0
     if rgb:
         b += npix * (3 + 1 / 8)
     if depth:
         b += npix * (2 + 1 / 8)
+    if fused or (depth and scaled):
+        b += npix * 2
     if fused:
-        b += npix * (2 + 1 / 8)
+        b += npix / 8
     return b
 
 
@@ -476,7 +480,8 @@ def bench_batch(args) -> int:
     full = sum(stream_bytes(sp, float(mean_holes[i]), M, esize, sp.rgb and sp.depth)
                for i, sp in enumerate(wl.streams))
     state = float(sum(int(r.sum().item()) for r in records)) / K
-    alg = state + sum(io_bytes_per_frame(sp.npix, sp.rgb, sp.depth, sp.rgb and sp.depth) for sp in wl.streams)
+    alg = state + sum(io_bytes_per_frame(sp.npix, sp.rgb, sp.depth, sp.rgb and sp.depth, dtype == "f32")
+                      for sp in wl.streams)
     achieved = alg / (ms_step / 1e3) / 1e9
     copy_gbs = device_copy_gbs(alg, stream, reps=20)
     traffic, trec = _traffic(args.workload, "batch") if dtype == "f32" else (None, None)

@@ -150,6 +150,11 @@ static ModelConsts make_consts(const gmm_config& c, int mod, int C, bool hole_sk
   k.hole_skip = hole_skip ? 1 : 0;
   k.rho_density = c.rho_mode == GMM_RHO_DENSITY ? 1 : 0;
   k.rho_scale = static_cast<float>(static_cast<double>(c.alpha) * std::pow(2.0 * M_PI, -0.5 * C));
+  // (1 / (1 - alpha))^(1, 2, 4, 8), each from the previous in fp32 (hole_factor)
+  k.dk[0] = 1.0f / k.oma;
+  k.dk[1] = k.dk[0] * k.dk[0];
+  k.dk[2] = k.dk[1] * k.dk[1];
+  k.dk[3] = k.dk[2] * k.dk[2];
   return k;
 }
 
@@ -201,7 +206,9 @@ gmm_status rgbd::new_handle(const gmm_config* cfg, gmm_handle** out) {
   h->rgb_bytes = is_augmented(h) ? round_up(tiles * tile_layout(M, 4, es).bytes, 256)
                                  : (has_rgb(h) ? round_up(tiles * tile_layout(M, 3, es).bytes, 256) : 0);
   h->depth_bytes = sep_depth(h) ? round_up(tiles * tile_layout(M, 1, es).bytes, 256) : 0;
-  h->fuse_bytes = sep_both(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
+  // one flags byte per pixel for a handle with a depth model: its List 1 state (two modalities)
+  // and its hole count (fp32 state)
+  h->fuse_bytes = sep_depth(h) ? static_cast<size_t>(round_up(h->npix, 256)) : 0;
   // below 2 GiB: the kernels address a block with 32-bit offsets and use offset 2^31 for "no access"
   if (std::max(h->rgb_bytes, h->depth_bytes) >= 0x80000000ull) {
     delete h;
@@ -223,7 +230,7 @@ void rgbd::place_state(gmm_handle* h, void* mem) {
   uint8_t* base = static_cast<uint8_t*>(mem);
   h->st_rgb = has_rgb(h) ? base : nullptr;
   h->st_depth = sep_depth(h) ? base + h->rgb_bytes : nullptr;
-  h->fstate = sep_both(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
+  h->fstate = sep_depth(h) ? base + h->rgb_bytes + h->depth_bytes : nullptr;
 }
 
 hipError_t rgbd::init_state(gmm_handle* h, hipStream_t s) {
@@ -232,7 +239,7 @@ hipError_t rgbd::init_state(gmm_handle* h, hipStream_t s) {
     e = launch_init(h->st_rgb, h->cfg.state_dtype, h->tiles64, h->cfg.M, is_augmented(h) ? 4 : 3, h->kc.var0, s);
   if (e == hipSuccess && sep_depth(h))
     e = launch_init(h->st_depth, h->cfg.state_dtype, h->tiles64, h->cfg.M, 1, h->kd.var0, s);
-  if (e == hipSuccess && sep_both(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, s);
+  if (e == hipSuccess && sep_depth(h)) e = launch_fill_u8(h->fstate, kFuseInit, h->fuse_bytes, s);
   return e;
 }
 
@@ -488,8 +495,11 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
     const size_t P = blk == 0 ? (is_augmented(h) ? 6 : 5) : 3;
     const uint32_t C = static_cast<uint32_t>(P - 2);
     const uint32_t es = static_cast<uint32_t>(h->esize);
-    // scaled weights: the weight is the tile's scale times the scaled weight (a product of two
-    // floats, exact in double)
+    // scaled weights: the weight is the pixel's effective scale (the tile's scale times the
+    // pixel's hole factor, one fp32 product as the kernels form it) times the scaled weight (a
+    // product of two floats, exact in double)
+    const uint8_t* flags = sep_depth(h) ? raw.data() + h->rgb_bytes + h->depth_bytes : nullptr;
+    const rgbd::ModelConsts& kcon = blk == 0 ? h->kc : h->kd;
     std::vector<double> scale;
     if (scaled_weights(es)) {
       try {
@@ -508,7 +518,11 @@ gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream) {
       for (size_t i = 0; i < n; ++i) {
         const size_t at = off + state_value_offset(v, i, h->tiles64, static_cast<uint32_t>(M), C, es);
         unpack_values(raw.data() + at, o + i, 1, h->cfg.state_dtype);
-        if (param == C + 1 && !scale.empty()) o[i] *= scale[i / kWave];
+        if (param == C + 1 && !scale.empty()) {
+          float gi = static_cast<float>(scale[i / kWave]);
+          if (blk == 1 && flags) gi = gi * hole_factor(flags[i] >> kHoleShift, kcon.dk);
+          o[i] *= static_cast<double>(gi);
+        }
       }
       o += n;
     }
@@ -570,6 +584,9 @@ gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream) {
       f[i] = static_cast<uint8_t>((static_cast<int>(c) + 3) | (static_cast<int>(I) << 3));
     }
     for (size_t i = n; i < h->fuse_bytes; ++i) f[i] = static_cast<uint8_t>(kFuseInit);
+  } else if (sep_depth(h)) {  // the flags bytes of a depth-only handle: no List 1 state, no holes counted
+    uint8_t* f = raw.data() + off;
+    for (size_t i = 0; i < h->fuse_bytes; ++i) f[i] = static_cast<uint8_t>(kFuseInit);
   }
   DeviceGuard g(h->cfg.device);
   if (!g.ok()) return fail(GMM_ERR_DEVICE, "cannot select the handle's device");

@@ -53,7 +53,23 @@ struct ModelConsts {
   int32_t hole_skip;  // depth: value 0 leaves the state untouched, pixel background
   int32_t rho_density;  // 0: mean/variance rate alpha; 1: alpha times the matched density
   float rho_scale;      // alpha (2 pi)^(-C/2), the constant factor of that density rate
+  float dk[4];          // (1 / (1 - alpha))^(1, 2, 4, 8) in fp32: factors of hole_factor
 };
+
+// A pixel's deferred hole frames (scaled form; see the Mix comment): up to kHoleMax, held in bits
+// 4-7 of the pixel's flags byte (bits 0-3 hold the List 1 state).
+constexpr uint32_t kHoleShift = 4, kHoleMax = 15;
+
+// (1 / (1 - alpha))^k for 0 <= k <= kHoleMax, as fp32 products in a fixed order, so that the host
+// (reading the state) and every kernel compute the same value.
+__host__ __device__ inline float hole_factor(uint32_t k, const float (&dk)[4]) {
+  float d = 1.f;
+  d = (k & 1u) ? d * dk[0] : d;
+  d = (k & 2u) ? d * dk[1] : d;
+  d = (k & 4u) ? d * dk[2] : d;
+  d = (k & 8u) ? d * dk[3] : d;
+  return d;
+}
 
 // ---- storage types of the mixture state --------------------------------------------------
 struct f16s { uint16_t b; };
@@ -95,12 +111,19 @@ template <> struct Storage<bf16s> {
 //                            component writes rank 0 alone. The form also stores the key of rank
 //                            1 (key1 = w'_1 / sigma_1, as the re-sort computes it), which such a
 //                            frame compares with rank 0's new key and never changes.
+//                            A frame in which a pixel keeps its state (a depth hole) must keep
+//                            each weight g * w' while g decays; instead of rescaling every w',
+//                            the pixel counts such frames, k, and its weights are d * g * w' with
+//                            d = (1 / (1 - alpha))^k (hole_factor): every step of the pixel works
+//                            with the effective scale d * g. k returns to 0 when the tile's scale
+//                            is folded, or when it would pass kHoleMax (the w' are then rescaled).
 template <int M, int C>
 struct Mix {
   float mu[C][M];
   float var[M];
   float w[M];
   float g;     // the tile's scale of the weights (scaled form only)
+  float d;     // the pixel's hole factor (scaled form only; 1 when k = 0)
   float key1;  // rank 1's key w'_1 / sigma_1 as stored (scaled form only)
 };
 
@@ -747,11 +770,12 @@ __device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const floa
 //   no match : the last rank becomes (x, sigma0^2, w_init)
 //   then     : w <- w / sum(w); re-sort by w/sigma descending; B = min{b : w_0+...+w_{b-1} > T};
 //              foreground = no match or new rank >= B
-// Scaled weights (SCALED): the decay of every weight is g <- (1-alpha) g, the tile's scale. After
-// a match the weights still sum to one, so the renormalisation changes nothing and only the
-// matched w' moves; after a replacement every w' is divided by g * sum(w'). Keys compare
-// w'/sigma, the same order as w/sigma (one positive scale per pixel). The new scale is left in
-// s.g and rank 1's key in s.key1.
+// Scaled weights (SCALED): the decay of every weight is g <- (1-alpha) g, the tile's scale; the
+// pixel works with its effective scale d g (d: its hole factor). After a match the weights still
+// sum to one, so the renormalisation changes nothing and only the matched w' moves; after a
+// replacement every w' is divided by (d g) sum(w'). Keys compare w'/sigma, the same order as
+// w/sigma (one positive scale per pixel). The tile's new scale is left in s.g, the pixel's hole
+// factor in s.d (1 after a fold) and rank 1's key in s.key1.
 // Re-sort: the renormalisation scales every unchanged weight by the same factor, so the
 // unchanged components keep their order and only the updated one (t) can be out of place. It
 // walks up past neighbours with a strictly smaller key and down past neighbours with a strictly
@@ -793,11 +817,12 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
     });
   });
   const float wj_old = wj;
-  float g1 = 1.f, inc = 0.f;
+  float g1 = 1.f, gt1 = 1.f, inc = 0.f;
   bool fold = false;
   if constexpr (SCALED) {
-    g1 = s.g * k.oma;
-    fold = !(g1 >= kMinScale);
+    gt1 = s.g * k.oma;       // the tile's next scale
+    fold = !(gt1 >= kMinScale);
+    g1 = gt1 * s.d;          // this pixel's next effective scale
     inc = k.alpha / g1;
   }
   update_matched<C, SCALED>(mj, vj, wj, d2j, x, k, inc);
@@ -825,10 +850,11 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       tw = tw * inv;
       gn = g1;
     } else {
-      // the weights as plain weights (g * w'), decayed, updated and renormalised; scale 1
+      // the weights as plain weights (d g w'), decayed, updated and renormalised; scale 1
+      const float ge = s.g * s.d;
       float wt[M];
-      static_for<0, M>([&](auto r_) RGBD_BODY { wt[RGBD_I(r_)] = s.g * s.w[RGBD_I(r_)]; });
-      tw = matched ? fmaf(k.oma, s.g * wj_old, k.alpha) : k.w_init;
+      static_for<0, M>([&](auto r_) RGBD_BODY { wt[RGBD_I(r_)] = ge * s.w[RGBD_I(r_)]; });
+      tw = matched ? fmaf(k.oma, ge * wj_old, k.alpha) : k.w_init;
       renormalise<M>(w, tw, wt, t, k.oma);
     }
   } else {
@@ -873,7 +899,9 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
       o.mu[c][r] = pick(r == q, tmu[c], mv);
     });
   });
-  o.g = gn;
+  // the tile's new scale, and the pixel's hole factor (a fold leaves plain weights: factor 1)
+  o.g = SCALED && !fold ? gt1 : 1.f;
+  o.d = SCALED && !fold ? s.d : 1.f;
   if constexpr (SCALED && M > 1) o.key1 = o.w[1] * __builtin_amdgcn_rsqf(o.var[1]);
   s = o;
 
@@ -891,15 +919,17 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
   return !matched || q >= B;
 }
 
-// The frame of a pixel that keeps its state (a depth hole), in the scaled form: the tile's scale
-// still moves to g (1 - alpha) (or folds to 1), so every w' is rescaled by the old scale over
-// the new one, which keeps each weight g * w'. Rank 1's key follows its w'.
+// The frame of a pixel that keeps its state (a depth hole), in the scaled form, when its hole
+// count cannot grow (or the tile's scale folds): every w' is rescaled by its effective scale
+// d g over the tile's new scale, which keeps each weight, and the hole factor returns to 1.
+// Rank 1's key follows its w'.
 template <int M, int C>
 __device__ __forceinline__ void hold_step(Mix<M, C>& s, const ModelConsts& k) {
   const float gn = next_scale(s.g, k);
-  const float f = s.g / gn;
+  const float f = (s.g * s.d) / gn;
   static_for<0, M>([&](auto r_) RGBD_BODY { s.w[RGBD_I(r_)] *= f; });
   s.g = gn;
+  s.d = 1.f;
   if constexpr (M > 1) s.key1 = s.w[1] * __builtin_amdgcn_rsqf(s.var[1]);
 }
 
@@ -922,11 +952,11 @@ __device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], con
   bool hit = (s.w[0] > 0.f) & (d2 < k.k2 * s.var[0]);
   float mj[C], vj = s.var[0], wj = s.w[0];
   static_for<0, C>([&](auto c_) RGBD_BODY { mj[RGBD_I(c_)] = s.mu[RGBD_I(c_)][0]; });
-  float g1 = 1.f, inc = 0.f;
+  float gt1 = 1.f, inc = 0.f;
   if constexpr (SCALED) {
-    g1 = s.g * k.oma;
-    hit = hit & (g1 >= kMinScale);
-    inc = k.alpha / g1;
+    gt1 = s.g * k.oma;                  // the tile's next scale
+    hit = hit & (gt1 >= kMinScale);     // a fold sends the pixel to mix_step
+    inc = k.alpha / (gt1 * s.d);        // over this pixel's next effective scale
   }
   update_matched<C, SCALED>(mj, vj, wj, d2, x, k, inc);
   // rank 0 keeps its place unless rank 1's key is strictly larger
@@ -935,7 +965,7 @@ __device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], con
     // rank 1's key as mix_step computes it (its w' and variance are unchanged after a match of
     // rank 0, and a match leaves the weights unscaled)
     if constexpr (M > 1) keeps = !(s.key1 > wj * __builtin_amdgcn_rsqf(vj));
-    s.g = g1;
+    s.g = gt1;
   } else {
     float w[M];
     renormalise<M>(w, wj, s.w, 0, k.oma);
@@ -949,7 +979,8 @@ __device__ __forceinline__ bool fast_step(Mix<M, C>& s, const float (&x)[C], con
 }
 
 // List 1 (Sec. III.C): one transition of the fused bit I and counter cpt of a pixel.
-// Encoded state byte: bits 0-2 hold cpt + 3 (0..6), bit 3 holds I.
+// Encoded state byte: bits 0-2 hold cpt + 3 (0..6), bit 3 holds I; bits 4-7 (a depth pixel's
+// hole count) pass through unchanged.
 __device__ __forceinline__ uint32_t fuse_transition(uint32_t st, bool r, bool d) {
   int c = static_cast<int>(st & 7u) - 3;
   bool I = (st >> 3) & 1u;
@@ -965,7 +996,7 @@ __device__ __forceinline__ uint32_t fuse_transition(uint32_t st, bool r, bool d)
   } else {
     c += (I == r) ? 1 : -1;
   }
-  return static_cast<uint32_t>(c + 3) | (static_cast<uint32_t>(I) << 3);
+  return static_cast<uint32_t>(c + 3) | (static_cast<uint32_t>(I) << 3) | (st & 0xF0u);
 }
 
 constexpr uint32_t kFuseInit = 3u;  // I = 0, cpt = 0

@@ -109,17 +109,35 @@ template <int M, int C, typename S>
 struct StepState {
   Mix<M, C> full;  // the whole state as read (general-path lanes)
   bool slow;       // this lane takes the general path
+  bool fold;       // the tile's scale folds this frame (scaled form; uniform over the wave)
   bool fg;         // its foreground bit
   int kept;        // the rank its updated component kept, or -1 when the ranks were reordered
+  uint32_t kout;   // the pixel's hole count after the frame (scaled form)
+  float gnext;     // the tile's scale after the frame (scaled form)
 };
 
+// `kin`: the pixel's hole count (scaled form; 0 where the caller keeps none). With `defer`, a lane
+// that keeps its state (valid, not active) only counts the frame while its count can grow and the
+// tile's scale does not fold; otherwise it takes hold_step.
 template <int M, int C, typename S, int CP = kCached>
 __device__ __forceinline__ void step_begin(Mix<M, C>& m, StepState<M, C, S>& st, const StateBlock& blk, uint32_t p,
-                                           bool valid, bool active, const float (&x)[C], const ModelConsts& k) {
+                                           bool valid, bool active, const float (&x)[C], const ModelConsts& k,
+                                           uint32_t kin, bool defer) {
   constexpr bool SC = kScaled<S>;
+  bool held = false;
+  st.fold = false;
+  if constexpr (SC) {
+    m.d = hole_factor(kin, k.dk);
+    // the same for every lane (one scale per tile): kept in a scalar register
+    st.gnext = __builtin_bit_cast(
+        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, next_scale(m.g, k))));
+    st.fold = !(m.g * k.oma >= kMinScale);
+    held = defer && valid && !active && kin < kHoleMax && !st.fold;
+  }
   st.full = m;  // the prefix as read (fast_step updates m in place)
   const bool fast = active && fast_step<M, C, SC>(m, x, k);
-  st.slow = SC ? valid && !fast : active && !fast;
+  st.slow = SC ? valid && !fast && !held : active && !fast;
+  st.kout = held ? kin + 1 : kin;
   load_rest<M, C, S, kFastLoad<M, C, S>, CP>(st.full, blk, p, st.slow);
 }
 
@@ -138,6 +156,8 @@ __device__ __forceinline__ void step_compute(Mix<M, C>& m, StepState<M, C, S>& s
       st.fg = mix_step<M, C, SC>(st.full, x, k, j, q, all);
     }
     st.kept = !all && (j < M ? j : M - 1) == q ? q : -1;
+    // hold_step and a fold leave the weights relative to the tile's scale alone
+    if (!active || st.fold) st.kout = 0;
     m = st.full;
   }
 }
@@ -165,8 +185,8 @@ __device__ __forceinline__ void step_store(const Mix<M, C>& m, const StepState<M
   store_mix<M, C, S, SF, true, kSuffixShared, CP>(m, blk, p, valid);
   if constexpr (rows_from_exist<M, C, SF, S>()) store_rows_from<M, C, S, SF, CP>(m, blk, p, slow);
   if constexpr (!kSuffixShared) store_suffix_of<M, C, S>(m, blk, p, slow, kept < 0, kept);
-  if constexpr (SC) {  // every valid lane holds the tile's new scale
-    store_scale(m.g, blk, p, valid && (p & 63u) == 0);
+  if constexpr (SC) {  // the tile's new scale, from its first lane
+    store_scale(st.gnext, blk, p, valid && (p & 63u) == 0);
     wave_bytes += 8u;
   }
   const uint32_t n_slow = __popcll(__ballot(slow)), n_valid = __popcll(__ballot(valid));
@@ -190,7 +210,7 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
                                               bool active, const float (&x)[C], const ModelConsts& k,
                                               uint32_t& wave_bytes) {
   StepState<M, C, S> st;
-  step_begin<M, C, S, CP>(m, st, blk, p, valid, active, x, k);
+  step_begin<M, C, S, CP>(m, st, blk, p, valid, active, x, k, 0u, false);
   step_compute<M, C, S>(m, st, active, x, k);
   step_store<M, C, S, CP>(m, st, blk, p, valid, wave_bytes);
   return st.fg;
@@ -236,7 +256,9 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   RgbLoad rl{};
   if (do_c) rl = issue_rgb_pixel<CP>(a, pc, wave_base, lane);
   const float xd = do_d ? load_depth_pixel<CP>(a, pc) : 0.f;
-  const uint32_t fst = do_f ? a.fstate[pc] : 0u;
+  // the flags byte: List 1 state (bits 0-3) and, in the scaled form, the depth hole count
+  constexpr bool do_flags = do_f || (kScaled<S> && do_d);
+  const uint32_t fst = do_flags ? a.fstate[pc] : 0u;
   if (do_c) load_prefix<M, 3, S, CP>(mc, blk_c, pc, true);
   if (do_d) load_prefix<M, 1, S, CP>(md, blk_d, pc, true);
   float x[3] = {0.f, 0.f, 0.f};
@@ -247,11 +269,11 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   StepState<M, 3, S> sc;
   StepState<M, 1, S> sd;
   if constexpr (do_c) {
-    step_begin<M, 3, S, CP>(mc, sc, blk_c, p, valid, valid, x, a.kc);
+    step_begin<M, 3, S, CP>(mc, sc, blk_c, p, valid, valid, x, a.kc, 0u, false);
     step_compute<M, 3, S>(mc, sc, valid, x, a.kc);
     fgc = sc.fg;
   }
-  if constexpr (do_d) step_begin<M, 1, S, CP>(md, sd, blk_d, p, valid, active_d, x1, a.kd);
+  if constexpr (do_d) step_begin<M, 1, S, CP>(md, sd, blk_d, p, valid, active_d, x1, a.kd, fst >> kHoleShift, true);
   if constexpr (do_c) step_store<M, 3, S, CP>(mc, sc, blk_c, p, valid, wave_bytes);
   if constexpr (do_d) {
     step_compute<M, 1, S>(md, sd, active_d, x1, a.kd);
@@ -260,10 +282,11 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   }
   // the List 1 step and the mask words last: their stores sit behind lane conditions
   bool fgf = false;
-  if (do_f && valid) {
-    const uint32_t st = fuse_transition(fst, fgc, fgd);
+  if (do_flags && valid) {
+    uint32_t st = do_f ? fuse_transition(fst, fgc, fgd) : fst;
+    if constexpr (kScaled<S> && do_d) st = (st & 0x0Fu) | (sd.kout << kHoleShift);
     a.fstate[p] = static_cast<uint8_t>(st);
-    fgf = (st >> 3) & 1u;
+    fgf = do_f && ((st >> 3) & 1u);
   }
   const uint64_t bc = __ballot(fgc), bd = __ballot(fgd), bf = __ballot(fgf);
   if (lane == 0 && valid) {

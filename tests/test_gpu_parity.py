@@ -451,11 +451,11 @@ def test_traffic_record_counts_only_the_changed_pieces():
 def test_traffic_record_counts_fast_and_full_lanes():
     """Traffic is decided per lane (M=5, fp32, scaled weights; each modality also reads and writes
     its tile's scale, 2 x 8 B per wave). Frame 0 matches nothing: every colour lane reads and
-    writes its whole state (2 x (26 values x 4 B) = 208 B), every depth lane too (2 x 64 B =
-    128 B; a depth hole rescales its weights to the tile's new scale, which also moves the whole
-    state). The same frame again matches rank 0 everywhere and keeps the order, so every lane
-    with a reading moves only rank 0 (+ rank 1's key on the read side), exactly: colour 24 + 20 B,
-    depth 16 + 12 B; a hole again 128 B."""
+    writes its whole state (2 x (26 values x 4 B) = 208 B), every depth lane with a reading too
+    (2 x 64 B = 128 B), while a depth hole only counts the frame in its flags byte: it moves the
+    fast rows, read and written back unchanged (16 + 12 B). The same frame again matches rank 0
+    everywhere and keeps the order, so every lane with a reading moves only rank 0 (+ rank 1's key
+    on the read side), exactly: colour 24 + 20 B, depth 16 + 12 B; a hole again 28 B."""
     spec = StreamSpec(160, 120, n_boxes=1, box_min=20, box_max=20, hole_p=0.05, seed=61)
     st = Stream(spec)
     seg = Segmenter(160, 120, GMM_RGB | GMM_DEPTH, 5)
@@ -467,11 +467,11 @@ def test_traffic_record_counts_fast_and_full_lanes():
         assert int(holes.sum()) > 0
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        first = torch.full_like(holes, 64 * 208 + 64 * 128 + 16)
+        first = 64 * 208 + (64 - holes) * 128 + holes * 28 + 16
         assert torch.equal(rec, first)
         seg.apply_fused(rgb, depth)
         torch.cuda.synchronize()
-        second = first + 64 * 44 + (64 - holes) * 28 + holes * 128 + 16
+        second = first + 64 * 44 + 64 * 28 + 16
         assert torch.equal(rec, second)
         _abi.gmm_set_traffic_record(seg.handle, None)
         seg.apply_fused(rgb, depth)
