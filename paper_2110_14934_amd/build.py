@@ -52,12 +52,36 @@ def _compile(src: str) -> str:
     return obj
 
 
+# Device-code checks that the GPU tests run: built with the library's flags, in-tree, next to
+# their sources (tests/<name>.hip -> tests/<name>).
+CHECKS = [os.path.join(ROOT, "tests", "paths_check.hip")]
+
+
+def check_path(src: str) -> str:
+    return os.path.splitext(src)[0]
+
+
+def _compile_check(src: str) -> str:
+    exe = check_path(src)
+    cmd = [hipcc(), *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", src, "-o", exe + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
 def build(verbose: bool = False) -> str:
-    """Compile and link the library; always rebuilds. Returns the library path."""
+    """Compile and link the library and the device-code checks; always rebuilds. Returns the
+    library path."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sources()
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    checks = [c for c in CHECKS if os.path.exists(c)]
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs) + len(checks))) as ex:
+        check_jobs = [ex.submit(_compile_check, c) for c in checks]
         objs = list(ex.map(_compile, srcs))
+        for j in check_jobs:
+            j.result()
     tmp = LIB_PATH + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -919,6 +919,50 @@ __device__ __forceinline__ bool mix_step(Mix<M, C>& s, const float (&x)[C], cons
   return !matched || q >= B;
 }
 
+// The frame of a pixel whose rank-0 component does not match x while its rank-1 component
+// does and keeps rank 1 (scaled form, the tile's scale not folding): on a mixture's second mode
+// most pixels that leave the fast path are such pixels. Computes exactly what mix_step computes
+// for them, with the same helpers and expressions (the matched weight moves by the increment and
+// no other weight changes, so the re-sort compares the updated key with rank 0's and rank 2's
+// only, and the pixel is foreground exactly when rank 0's weight alone passes T), without the
+// gather over the ranks and the permutation. Returns whether the pixel is such a pixel; if so,
+// `s` holds its new state and `fg` its foreground bit, else `s` is unchanged.
+template <int M, int C>
+__device__ __forceinline__ bool rank1_step(Mix<M, C>& s, const float (&x)[C], const ModelConsts& k, bool& fg) {
+  static_assert(M > 1, "a second rank");
+  float d20 = 0.f, d21 = 0.f;
+  static_for<0, C>([&](auto c_) RGBD_BODY {
+    constexpr int c = RGBD_I(c_);
+    const float t0 = x[c] - s.mu[c][0];
+    d20 = fmaf(t0, t0, d20);
+    const float t1 = x[c] - s.mu[c][1];
+    d21 = fmaf(t1, t1, d21);
+  });
+  const bool hit0 = (s.w[0] > 0.f) & (d20 < k.k2 * s.var[0]);
+  const bool hit1 = (s.w[1] > 0.f) & (d21 < k.k2 * s.var[1]);
+  const float gt1 = s.g * k.oma;
+  const bool fold = !(gt1 >= kMinScale);
+  const float g1 = gt1 * s.d;
+  const float inc = k.alpha / g1;
+  float mj[C], vj = s.var[1], wj = s.w[1];
+  static_for<0, C>([&](auto c_) RGBD_BODY { mj[RGBD_I(c_)] = s.mu[RGBD_I(c_)][1]; });
+  update_matched<C, true>(mj, vj, wj, d21, x, k, inc);
+  const float kt = wj * __builtin_amdgcn_rsqf(vj);
+  const bool up = s.w[0] * __builtin_amdgcn_rsqf(s.var[0]) < kt;
+  bool down = false;
+  if constexpr (M > 2) down = s.w[2] * __builtin_amdgcn_rsqf(s.var[2]) > kt;
+  const bool ok = !hit0 & hit1 & !fold & !up & !down;
+  if (ok) {
+    static_for<0, C>([&](auto c_) RGBD_BODY { s.mu[RGBD_I(c_)][1] = mj[RGBD_I(c_)]; });
+    s.var[1] = vj;
+    s.w[1] = wj;
+    s.key1 = kt;
+    s.g = gt1;
+    fg = g1 * s.w[0] > k.T;
+  }
+  return ok;
+}
+
 // The frame of a pixel that keeps its state (a depth hole), in the scaled form, when its hole
 // count cannot grow (or the tile's scale folds): every w' is rescaled by its effective scale
 // d g over the tile's new scale, which keeps each weight, and the hole factor returns to 1.

@@ -153,7 +153,16 @@ __device__ __forceinline__ void step_compute(Mix<M, C>& m, StepState<M, C, S>& s
     if (SC && !active) {
       if constexpr (SC) hold_step<M, C>(st.full, k);
     } else {
-      st.fg = mix_step<M, C, SC>(st.full, x, k, j, q, all);
+      // a match of rank 1 that keeps its rank takes the short step; mix_step runs only for the
+      // lanes it does not cover (and not at all in a wave with none)
+      bool done = false;
+      if constexpr (SC && M > 1) done = rank1_step<M, C>(st.full, x, k, st.fg);
+      if (done) {
+        j = q = 1;
+        all = false;
+      } else {
+        st.fg = mix_step<M, C, SC>(st.full, x, k, j, q, all);
+      }
     }
     st.kept = !all && (j < M ? j : M - 1) == q ? q : -1;
     // hold_step and a fold leave the weights relative to the tile's scale alone

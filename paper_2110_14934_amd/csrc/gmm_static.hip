@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(64) pack_kernel(PackArgs p, FrameArgs* __restr
 }
 
 template <int M, typename S, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) batch_search_kernel(const FrameArgs* __restrict__ table,
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) batch_search_kernel(const FrameArgs* __restrict__ table,
                                                              const uint32_t* __restrict__ first,
                                                              uint32_t n_streams, uint32_t n_tiles,
                                                              uint32_t tile_px) {
