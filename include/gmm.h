@@ -192,17 +192,19 @@ gmm_status gmm_state_size(const gmm_handle* h, size_t* n_doubles);
 
 /*
  * Copy the state out in the canonical layout (host memory, float64). Synchronises `stream`.
- * fp32 state keeps each pixel's weights as one scale times per-component scaled weights (a
- * frame's common decay of every weight goes into the scale alone); the canonical weight is their
- * product, exact in float64. Every other value is copied exactly.
+ * fp32 state keeps the weights of each 64-pixel tile as one scale times per-component scaled
+ * weights (a frame's common decay of every weight goes into the scale alone); a depth pixel
+ * that kept its state through k missing readings carries the factor (1/(1-alpha))^k besides.
+ * The canonical weight is the fp32 product of scale and factor (as the kernels form it) times
+ * the scaled weight, exact in float64. Every other value is copied exactly.
  */
 gmm_status gmm_read_state(gmm_handle* h, double* host_out, void* stream);
 
 /*
  * Replace the state from the canonical layout (host memory, float64), rounding each value to
- * the storage type to nearest, ties to even (fp32 weights are stored with scale 1, so a read
- * followed by a write can change the low bits of the weights). I must be 0 or 1 and cpt in
- * [-3, 3], else GMM_ERR_INVALID_ARG. Synchronises `stream`.
+ * the storage type to nearest, ties to even (fp32 weights are stored with scale 1 and no
+ * missing-reading factor, so a read followed by a write can change the low bits of the
+ * weights). I must be 0 or 1 and cpt in [-3, 3], else GMM_ERR_INVALID_ARG. Synchronises `stream`.
  */
 gmm_status gmm_write_state(gmm_handle* h, const double* host_in, void* stream);
 

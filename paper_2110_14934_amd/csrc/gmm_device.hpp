@@ -1,9 +1,10 @@
 // Device-side building blocks of the per-pixel mixture step (gfx950, wave64).
 //
-// One lane owns one pixel of one modality. Its M components are loaded from the two-plane state
-// layout (below: rows of 16-byte chunks shared by the 64 lanes of a tile, tile after tile, then
-// each pixel's remaining values contiguous in a second plane), advanced one frame in fp32
-// registers, re-sorted in registers and written back.
+// One lane owns one pixel of one modality. Its M components are loaded from the planar state
+// layout (below: rows of 16-, 8- or 4-byte pieces shared by the 64 lanes of a tile, tile after
+// tile, then each pixel's remaining values contiguous in a second plane, and in fp32 state one
+// weight scale per tile in a third), advanced one frame in fp32 registers, re-sorted in
+// registers and written back.
 // Every kernel of the library (plain, fused, batched) calls the same functions below, so all
 // of them produce bit-identical results for the same pixel.
 #pragma once
@@ -774,7 +775,7 @@ __device__ __forceinline__ void renormalise(float (&w)[M], float& tw, const floa
 // pixel works with its effective scale d g (d: its hole factor). After a match the weights still
 // sum to one, so the renormalisation changes nothing and only the matched w' moves; after a
 // replacement every w' is divided by (d g) sum(w'). Keys compare w'/sigma, the same order as
-// w/sigma (one positive scale per pixel). The tile's new scale is left in s.g, the pixel's hole
+// w/sigma (one positive effective scale per pixel). The tile's new scale is left in s.g, the pixel's hole
 // factor in s.d (1 after a fold) and rank 1's key in s.key1.
 // Re-sort: the renormalisation scales every unchanged weight by the same factor, so the
 // unchanged components keep their order and only the updated one (t) can be out of place. It

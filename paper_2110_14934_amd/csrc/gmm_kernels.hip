@@ -4,10 +4,10 @@
 // its foreground bits form exactly one uint64 word of the output mask (one ballot, one store).
 // The interleaved RGB8 input of a wave (192 contiguous bytes when rows are dense) is staged
 // through LDS with 48 dword loads and de-interleaved on chip - the structure-of-arrays split of
-// the colour image done without a separate pass. The state is kept in two planes per modality:
-// chunk rows of the fast-path values (a wave's row load or store moves 1 KB of contiguous memory,
-// and the rows of consecutive waves follow each other), then each pixel's remaining values,
-// contiguous per pixel.
+// the colour image done without a separate pass. The state is kept in planes per modality (see
+// gmm_device.hpp): rows of the fast-path values (a wave's row load or store moves up to 1 KB of
+// contiguous memory, and the rows of consecutive waves follow each other), then each pixel's
+// remaining values, contiguous per pixel, then (fp32 state) one weight scale per 64-pixel tile.
 #include <hip/hip_runtime.h>
 
 #include "gmm_device.hpp"
