@@ -169,9 +169,15 @@ const char* gmm_last_error(void);
  * Measurement aid: when `wave_bytes` is a device array of ceil(width*height/64) uint64, every
  * later launch on this handle (plain or batched) ADDS to entry i the bytes of mixture state that
  * wave i (pixels 64i..64i+63) read and wrote. The traffic of a frame depends on the data: a
- * pixel that matches its top-ranked component and keeps it moves only the weights and that
- * component (and reads the second rank's variance); any other pixel reads and writes its whole
- * state. NULL stops recording. The caller owns (and zeroes) the array.
+ * pixel that matches its top-ranked component and keeps it reads what decides that (the second
+ * rank's variance, or in the fp32 form its stored key and the tile's scale) and writes only what
+ * the step changed; any other pixel reads its whole state and writes the values that changed.
+ * NULL stops recording. The caller owns (and zeroes) the array.
+ * Batched launches copy the record pointer into their descriptors when these are prepared
+ * (gmm_batch_set_frames; every gmm_batch_apply, gmm_batch_apply_static and executor tick), and a launch runs
+ * the counting kernel only when one of its descriptors carries a record: a batched launch captured
+ * into a graph before the slots were prepared with the record keeps the kernel that does not
+ * count, so capture again after preparing them.
  */
 gmm_status gmm_set_traffic_record(gmm_handle* h, uint64_t* wave_bytes);
 

@@ -28,8 +28,10 @@
 
 namespace rgbd {
 
-// Five waves per SIMD: the body fits them without spilling (checked at build time by the tests)
-template <int M, typename S, int BLOCK>
+// Five waves per SIMD: the body fits them without spilling (checked at build time by the tests).
+// MEASURE: the body that adds each wave's state bytes to the streams' traffic records; the launch
+// takes it only when a stream of the batch has one, so the common body never forms the counts.
+template <int M, typename S, int BLOCK, bool MEASURE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) batch_kernel(const FrameArgs* __restrict__ table,
                                                       const uint32_t* __restrict__ tile_map,
                                                       const uint32_t* __restrict__ first_tile,
@@ -41,43 +43,51 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
     const uint32_t s = tile_map[t];
     const FrameArgs a = table[s];
     const uint32_t t0 = (t - first_tile[s]) * tile_px;
-    process_tile<M, S, BLOCK>(a, t0, tile_px, lane, lds[wv]);
+    process_tile<M, S, BLOCK, MEASURE>(a, t0, tile_px, lane, lds[wv]);
   }
 }
 
-template <int M, typename S>
-static hipError_t launch_batch_ms(int block, dim3 grid, const FrameArgs* table, const uint32_t* map,
-                                  const uint32_t* first, uint32_t n_tiles, uint32_t tile_px,
-                                  hipStream_t s) {
+template <int M, typename S, bool MEASURE>
+static hipError_t launch_batch_msm(int block, dim3 grid, const FrameArgs* table, const uint32_t* map,
+                                   const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, hipStream_t s) {
   if (block == 256)
-    batch_kernel<M, S, 256><<<grid, dim3(256), 0, s>>>(table, map, first, n_tiles, tile_px);
+    batch_kernel<M, S, 256, MEASURE><<<grid, dim3(256), 0, s>>>(table, map, first, n_tiles, tile_px);
   else if (block == 512)
-    batch_kernel<M, S, 512><<<grid, dim3(512), 0, s>>>(table, map, first, n_tiles, tile_px);
+    batch_kernel<M, S, 512, MEASURE><<<grid, dim3(512), 0, s>>>(table, map, first, n_tiles, tile_px);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+template <int M, typename S>
+static hipError_t launch_batch_ms(int block, dim3 grid, const FrameArgs* table, const uint32_t* map,
+                                  const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, bool measure,
+                                  hipStream_t s) {
+  return measure ? launch_batch_msm<M, S, true>(block, grid, table, map, first, n_tiles, tile_px, s)
+                 : launch_batch_msm<M, S, false>(block, grid, table, map, first, n_tiles, tile_px, s);
+}
+
 template <typename S>
 static hipError_t launch_batch_s(int M, int block, dim3 grid, const FrameArgs* table, const uint32_t* map,
-                                 const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, hipStream_t s) {
+                                 const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, bool measure,
+                                 hipStream_t s) {
   switch (M) {
-    case 1: return launch_batch_ms<1, S>(block, grid, table, map, first, n_tiles, tile_px, s);
-    case 2: return launch_batch_ms<2, S>(block, grid, table, map, first, n_tiles, tile_px, s);
-    case 3: return launch_batch_ms<3, S>(block, grid, table, map, first, n_tiles, tile_px, s);
-    case 4: return launch_batch_ms<4, S>(block, grid, table, map, first, n_tiles, tile_px, s);
-    case 5: return launch_batch_ms<5, S>(block, grid, table, map, first, n_tiles, tile_px, s);
+    case 1: return launch_batch_ms<1, S>(block, grid, table, map, first, n_tiles, tile_px, measure, s);
+    case 2: return launch_batch_ms<2, S>(block, grid, table, map, first, n_tiles, tile_px, measure, s);
+    case 3: return launch_batch_ms<3, S>(block, grid, table, map, first, n_tiles, tile_px, measure, s);
+    case 4: return launch_batch_ms<4, S>(block, grid, table, map, first, n_tiles, tile_px, measure, s);
+    case 5: return launch_batch_ms<5, S>(block, grid, table, map, first, n_tiles, tile_px, measure, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_batch(int M, int dtype, int block, dim3 grid, const FrameArgs* table,
                                const uint32_t* map, const uint32_t* first, uint32_t n_tiles,
-                               uint32_t tile_px, hipStream_t s) {
+                               uint32_t tile_px, bool measure, hipStream_t s) {
   switch (dtype) {
-    case GMM_F32: return launch_batch_s<float>(M, block, grid, table, map, first, n_tiles, tile_px, s);
-    case GMM_F16: return launch_batch_s<f16s>(M, block, grid, table, map, first, n_tiles, tile_px, s);
-    case GMM_BF16: return launch_batch_s<bf16s>(M, block, grid, table, map, first, n_tiles, tile_px, s);
+    case GMM_F32: return launch_batch_s<float>(M, block, grid, table, map, first, n_tiles, tile_px, measure, s);
+    case GMM_F16: return launch_batch_s<f16s>(M, block, grid, table, map, first, n_tiles, tile_px, measure, s);
+    case GMM_BF16: return launch_batch_s<bf16s>(M, block, grid, table, map, first, n_tiles, tile_px, measure, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -101,6 +111,7 @@ struct gmm_batch {
   std::vector<FrameArgs*> h_staging;         // pinned, one per slot
   std::vector<hipEvent_t> staging_done;      // last upload from each staging buffer
   std::vector<uint8_t> slot_ready;
+  std::vector<uint8_t> slot_measure;         // a stream of the slot's descriptors has a traffic record
   uint32_t* d_tile_map = nullptr;
   size_t tile_map_cap = 0;
   uint32_t* d_first_tile = nullptr;
@@ -166,7 +177,8 @@ static hipError_t run_slot(gmm_batch* b, int slot, hipStream_t s) {
   const uint32_t want = static_cast<uint32_t>(b->tuning.blocks_per_cu) * static_cast<uint32_t>(b->cu_count);
   const dim3 grid(std::max(1u, std::min(want, b->n_tiles)));
   return launch_batch(b->M, b->dtype, b->tuning.block_threads, grid, b->d_table + static_cast<size_t>(slot) * n_streams(b),
-                      b->d_tile_map, b->d_first_tile, b->n_tiles, static_cast<uint32_t>(b->tuning.tile_pixels), s);
+                      b->d_tile_map, b->d_first_tile, b->n_tiles, static_cast<uint32_t>(b->tuning.tile_pixels),
+                      b->slot_measure[slot] != 0, s);
 }
 
 static void free_batch(gmm_batch* b) {
@@ -241,6 +253,7 @@ gmm_status gmm_batch_create(gmm_handle* const* handles, int32_t n, int32_t n_slo
   b->h_staging.assign(n_slots, nullptr);
   b->staging_done.assign(n_slots, nullptr);
   b->slot_ready.assign(n_slots, 0);
+  b->slot_measure.assign(n_slots, 0);
   for (int32_t s = 0; s < n_slots; ++s) {
     e = hipHostMalloc(reinterpret_cast<void**>(&b->h_staging[s]), static_cast<size_t>(n) * sizeof(FrameArgs),
                       hipHostMallocDefault);
@@ -311,10 +324,12 @@ gmm_status gmm_batch_set_frames(gmm_batch* b, int32_t slot, const gmm_stream_io*
   hipError_t e = hipEventSynchronize(b->staging_done[slot]);  // previous upload from this buffer
   if (e != hipSuccess) return hip_fail(e, "staging event");
   FrameArgs* host = b->h_staging[slot];
+  bool measure = false;
   for (size_t i = 0; i < n_streams(b); ++i) {
     const gmm_stream_io& s = io[i];
     host[i] = frame_args(b->handles[i], s.rgb, s.rgb_pitch_bytes, s.depth, s.depth_pitch_bytes, s.fg_rgb,
                          s.fg_depth, s.fused);
+    measure = measure || host[i].wave_bytes != nullptr;
   }
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const size_t bytes = n_streams(b) * sizeof(FrameArgs);
@@ -322,6 +337,7 @@ gmm_status gmm_batch_set_frames(gmm_batch* b, int32_t slot, const gmm_stream_io*
   if (e == hipSuccess) e = hipEventRecord(b->staging_done[slot], hs);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   b->slot_ready[slot] = 1;
+  b->slot_measure[slot] = measure ? 1 : 0;
   b->last_stream = hs;
   return GMM_OK;
 }

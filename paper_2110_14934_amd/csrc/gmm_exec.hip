@@ -374,6 +374,7 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
   s.outs.clear();
   uint32_t* h_first = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s.h_table) + tab);
   uint64_t total_tiles = 0;
+  bool measure = false;
   for (int32_t i = 0; i < n; ++i) {
     const gmm_exec_item& it = items[i];
     gmm_handle* h = it.handle;
@@ -381,6 +382,7 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     const int k = static_cast<int>(att[i].frames % kFramesInFlight);
     s.h_table[i] = frame_args(h, att[i].d_rgb[k], 3 * static_cast<int64_t>(h->cfg.width), att[i].d_depth[k],
                               2 * static_cast<int64_t>(h->cfg.width), dm(0), dm(1), dm(2));
+    measure = measure || s.h_table[i].wave_bytes != nullptr;
     const size_t mb = mask_bytes(h);
     if (it.host_fg_rgb) s.outs.push_back({it.host_fg_rgb, moff[3 * i], mb});
     if (it.host_fg_depth) s.outs.push_back({it.host_fg_depth, moff[3 * i + 1], mb});
@@ -435,7 +437,7 @@ gmm_status gmm_exec_launch(gmm_exec* x, const gmm_exec_item* items, int32_t n, u
     const uint32_t want = static_cast<uint32_t>(tun.blocks_per_cu) * static_cast<uint32_t>(x->cu_count);
     const dim3 grid(std::max(1u, std::min(want, static_cast<uint32_t>(total_tiles))));
     e = launch_batch(x->M, x->dtype, tun.block_threads, grid, d_tab, s.d_tile_map, d_first,
-                     static_cast<uint32_t>(total_tiles), tile_px, x->s_compute);
+                     static_cast<uint32_t>(total_tiles), tile_px, measure, x->s_compute);
   }
   if (e == hipSuccess) e = hipEventRecord(s.compute_done, x->s_compute);
   // copy-out: the whole mask arena in one copy; the completion thread scatters it

@@ -21,18 +21,28 @@ struct RgbLoad {
   uint32_t b0, b1, b2;  // per lane: the pixel's bytes
 };
 
-template <int CP = kCached>
+// A bit that a batched launch adds to the mode of a tile whose frames are dense (a.rgb_dense and
+// a.depth_dense for the modalities present): such a body reads pixel p of a frame at 3p or 2p
+// bytes, with no row arithmetic and no per-stream test.
+constexpr int kFramesDense = 16;
+
+template <int CP = kCached, bool DENSE = false>
 __device__ __forceinline__ RgbLoad issue_rgb_pixel(const FrameArgs& a, uint32_t p, uint32_t wave_base, int lane) {
   RgbLoad r{};
-  r.staged = a.rgb_dense && (wave_base + kWave <= a.npix);
+  r.staged = (DENSE || a.rgb_dense) && (wave_base + kWave <= a.npix);
   if (r.staged) {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.rgb + 3 * static_cast<uint64_t>(wave_base));
     if constexpr (CP == kStream) r.w = __builtin_nontemporal_load(&src[lane < 48 ? lane : 47]);
     else r.w = src[lane < 48 ? lane : 47];
   } else {
-    const uint32_t y = p / static_cast<uint32_t>(a.width);
-    const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
-    const uint8_t* b = a.rgb + static_cast<int64_t>(y) * a.rgb_pitch + 3 * xx;
+    const uint8_t* b;
+    if constexpr (DENSE) {
+      b = a.rgb + 3 * static_cast<uint64_t>(p);
+    } else {
+      const uint32_t y = p / static_cast<uint32_t>(a.width);
+      const uint32_t xx = p - y * static_cast<uint32_t>(a.width);
+      b = a.rgb + static_cast<int64_t>(y) * a.rgb_pitch + 3 * xx;
+    }
     r.b0 = b[0];
     r.b1 = b[1];
     r.b2 = b[2];
@@ -65,9 +75,9 @@ __device__ __forceinline__ void load_rgb_pixel(const FrameArgs& a, uint32_t p, u
   if (!valid) x[0] = x[1] = x[2] = 0.f;
 }
 
-template <int CP = kCached>
+template <int CP = kCached, bool DENSE = false>
 __device__ __forceinline__ float load_depth_pixel(const FrameArgs& a, uint32_t p) {
-  if (a.depth_dense) {
+  if (DENSE || a.depth_dense) {
     if constexpr (CP == kStream) return static_cast<float>(__builtin_nontemporal_load(&a.depth[p]));
     else return static_cast<float>(a.depth[p]);
   }
@@ -225,13 +235,30 @@ __device__ __forceinline__ bool step_modality(Mix<M, C>& m, const StateBlock& bl
   return st.fg;
 }
 
+// The depth step's constants. The mixture parameters both modalities share (alpha, k, T, the
+// new component's weight, the rate variant and the hole factors) are the same numbers in a.kc and
+// a.kd (one configuration makes both); they are read from a.kc alone, so that a kernel keeps one
+// copy of them in scalar registers. Only sigma0, the variance floor, the hole policy and the
+// density factor are depth's own.
+__device__ __forceinline__ ModelConsts depth_consts(const FrameArgs& a) {
+  ModelConsts k = a.kc;
+  k.var0 = a.kd.var0;
+  k.var_min = a.kd.var_min;
+  k.hole_skip = a.kd.hole_skip;
+  k.rho_scale = a.kd.rho_scale;
+  return k;
+}
+
 // Pixel p of stream `a` (p may lie past the end: such lanes only take part in the ballots).
-// MODE (a compile-time combination of kModeRGB, kModeDepth, kModeFuse, or kModeAug alone) selects
-// the steps, so that no branch on it stands between the memory instructions. kModeAug is the
+// MODE (a compile-time combination of kModeRGB, kModeDepth, kModeFuse and kFramesDense, or kModeAug
+// alone) selects the steps, so that no branch on it stands between the memory instructions. kModeAug is the
 // four-channel variant:
 // one mixture over (R, G, B, D8) with D8 = min(255, depth >> 4), the augmentation the paper
 // describes and rejects in Sec. III.B; its mask goes to fg_rgb.
-template <int M, typename S, int MODE, int CP>
+// MEASURE: the body adds the wave's state bytes to a.wave_bytes when the stream has a traffic
+// record; without it the byte count is never formed (the batched launches take that body unless a
+// stream of the batch records).
+template <int M, typename S, int MODE, int CP, bool MEASURE = true>
 __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, int lane, uint32_t* lds_wave) {
   const uint32_t wave_base = p - lane;
   const bool valid = p < a.npix;
@@ -262,9 +289,10 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   // count down in issue order, so the wait for the colour bytes, which the LDS staging needs at
   // once, covers only them while the state prefixes stay in flight.
   const uint32_t pc = valid ? p : a.npix - 1;
+  constexpr bool dense = (MODE & kFramesDense) != 0;
   RgbLoad rl{};
-  if (do_c) rl = issue_rgb_pixel<CP>(a, pc, wave_base, lane);
-  const float xd = do_d ? load_depth_pixel<CP>(a, pc) : 0.f;
+  if (do_c) rl = issue_rgb_pixel<CP, dense>(a, pc, wave_base, lane);
+  const float xd = do_d ? load_depth_pixel<CP, dense>(a, pc) : 0.f;
   // the flags byte: List 1 state (bits 0-3) and, in the scaled form, the depth hole count
   constexpr bool do_flags = do_f || (kScaled<S> && do_d);
   const uint32_t fst = do_flags ? a.fstate[pc] : 0u;
@@ -272,7 +300,8 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
   if (do_d) load_prefix<M, 1, S, CP>(md, blk_d, pc, true);
   float x[3] = {0.f, 0.f, 0.f};
   if (do_c) finish_rgb_pixel(rl, lane, lds_wave, x);
-  const bool active_d = valid && !(a.kd.hole_skip && xd == 0.f);
+  const ModelConsts kd = depth_consts(a);
+  const bool active_d = valid && !(kd.hole_skip && xd == 0.f);
   const float x1[1] = {xd};
   // colour computed before depth's loads go out, colour written back after them
   StepState<M, 3, S> sc;
@@ -282,10 +311,10 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
     step_compute<M, 3, S>(mc, sc, valid, x, a.kc);
     fgc = sc.fg;
   }
-  if constexpr (do_d) step_begin<M, 1, S, CP>(md, sd, blk_d, p, valid, active_d, x1, a.kd, fst >> kHoleShift, true);
+  if constexpr (do_d) step_begin<M, 1, S, CP>(md, sd, blk_d, p, valid, active_d, x1, kd, fst >> kHoleShift, true);
   if constexpr (do_c) step_store<M, 3, S, CP>(mc, sc, blk_c, p, valid, wave_bytes);
   if constexpr (do_d) {
-    step_compute<M, 1, S>(md, sd, active_d, x1, a.kd);
+    step_compute<M, 1, S>(md, sd, active_d, x1, kd);
     fgd = sd.fg;
     step_store<M, 1, S, CP>(md, sd, blk_d, p, valid, wave_bytes);
   }
@@ -304,35 +333,38 @@ __device__ __forceinline__ void process_pixel(const FrameArgs& a, uint32_t p, in
     if (do_f) a.fused[wave_base >> 6] = bf;
   }
   // one wave owns each entry, and launches on a handle are ordered: a plain add is exact
-  if (a.wave_bytes != nullptr && lane == 0 && valid) a.wave_bytes[wave_base >> 6] += wave_bytes;
+  if constexpr (MEASURE)
+    if (a.wave_bytes != nullptr && lane == 0 && valid) a.wave_bytes[wave_base >> 6] += wave_bytes;
 }
 
 // Pixels [t0, t0 + tile_px) of stream `a` (tile_px a multiple of BLOCK; the part past the
 // stream's end is skipped), BLOCK at a time, the stream's mode resolved once for the tile. A
 // batched launch serves many streams, whose state together far exceeds the caches: its rows and
 // frames stream (kStream).
-template <int M, typename S, int MODE, int BLOCK>
+template <int M, typename S, int MODE, int BLOCK, bool MEASURE>
 __device__ __forceinline__ void process_tile_mode(const FrameArgs& a, uint32_t t0, uint32_t tile_px, int lane,
                                                   uint32_t* lds_wave) {
   for (uint32_t sub = 0; sub < tile_px; sub += BLOCK) {
     const uint32_t base = t0 + sub;
     if (base >= a.npix) break;  // uniform: the rest of the tile is past the stream's end
-    process_pixel<M, S, MODE, kStream>(a, base + threadIdx.x, lane, lds_wave);
+    process_pixel<M, S, MODE, kStream, MEASURE>(a, base + threadIdx.x, lane, lds_wave);
   }
 }
 
-template <int M, typename S, int BLOCK>
+template <int M, typename S, int BLOCK, bool MEASURE>
 __device__ __forceinline__ void process_tile(const FrameArgs& a, uint32_t t0, uint32_t tile_px, int lane,
                                              uint32_t* lds_wave) {
-  switch (a.mode) {  // the modes a batch accepts
-    case kModeRGB | kModeDepth | kModeFuse:
-      process_tile_mode<M, S, kModeRGB | kModeDepth | kModeFuse, BLOCK>(a, t0, tile_px, lane, lds_wave);
-      break;
-    case kModeRGB | kModeDepth:
-      process_tile_mode<M, S, kModeRGB | kModeDepth, BLOCK>(a, t0, tile_px, lane, lds_wave);
-      break;
-    case kModeRGB: process_tile_mode<M, S, kModeRGB, BLOCK>(a, t0, tile_px, lane, lds_wave); break;
-    case kModeDepth: process_tile_mode<M, S, kModeDepth, BLOCK>(a, t0, tile_px, lane, lds_wave); break;
+  constexpr int RGBD = kModeRGB | kModeDepth, FUSED = RGBD | kModeFuse, DN = kFramesDense;
+  const bool dense = ((a.mode & kModeRGB) == 0 || a.rgb_dense) && ((a.mode & kModeDepth) == 0 || a.depth_dense);
+  switch (a.mode | (dense ? DN : 0)) {  // the modes a batch accepts
+    case FUSED | DN: process_tile_mode<M, S, FUSED | DN, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case FUSED: process_tile_mode<M, S, FUSED, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case RGBD | DN: process_tile_mode<M, S, RGBD | DN, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case RGBD: process_tile_mode<M, S, RGBD, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case kModeRGB | DN: process_tile_mode<M, S, kModeRGB | DN, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case kModeRGB: process_tile_mode<M, S, kModeRGB, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case kModeDepth | DN: process_tile_mode<M, S, kModeDepth | DN, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
+    case kModeDepth: process_tile_mode<M, S, kModeDepth, BLOCK, MEASURE>(a, t0, tile_px, lane, lds_wave); break;
     default: break;
   }
 }

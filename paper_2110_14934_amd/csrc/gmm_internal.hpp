@@ -52,8 +52,10 @@ hipError_t launch_rekey(void* st, int dtype, uint32_t tiles64, int M, int C, hip
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 
 bool frame_variant_compiled(int M, int dtype);
+// `measure`: some descriptor of the table has a traffic record (wave_bytes); otherwise the kernel
+// that never counts bytes runs.
 hipError_t launch_batch(int M, int dtype, int block, dim3 grid, const FrameArgs* table, const uint32_t* map,
-                        const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, hipStream_t s);
+                        const uint32_t* first, uint32_t n_tiles, uint32_t tile_px, bool measure, hipStream_t s);
 
 inline size_t dtype_size(int dtype) { return dtype == GMM_F32 ? 4 : 2; }
 

@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(64) pack_kernel(PackArgs p, FrameArgs* __restr
   }
 }
 
-template <int M, typename S, int BLOCK>
+template <int M, typename S, int BLOCK, bool MEASURE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) batch_search_kernel(const FrameArgs* __restrict__ table,
                                                              const uint32_t* __restrict__ first,
                                                              uint32_t n_streams, uint32_t n_tiles,
@@ -67,42 +67,50 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
     }
     const FrameArgs a = table[lo];
     const uint32_t t0 = (t - first[lo]) * tile_px;
-    process_tile<M, S, BLOCK>(a, t0, tile_px, lane, lds[wv]);
+    process_tile<M, S, BLOCK, MEASURE>(a, t0, tile_px, lane, lds[wv]);
   }
 }
 
-template <int M, typename S>
-static hipError_t launch_search_ms(int block, dim3 grid, const FrameArgs* table, const uint32_t* first,
-                                   uint32_t n, uint32_t n_tiles, uint32_t tile_px, hipStream_t s) {
+template <int M, typename S, bool MEASURE>
+static hipError_t launch_search_msm(int block, dim3 grid, const FrameArgs* table, const uint32_t* first,
+                                    uint32_t n, uint32_t n_tiles, uint32_t tile_px, hipStream_t s) {
   if (block == 256)
-    batch_search_kernel<M, S, 256><<<grid, dim3(256), 0, s>>>(table, first, n, n_tiles, tile_px);
+    batch_search_kernel<M, S, 256, MEASURE><<<grid, dim3(256), 0, s>>>(table, first, n, n_tiles, tile_px);
   else if (block == 512)
-    batch_search_kernel<M, S, 512><<<grid, dim3(512), 0, s>>>(table, first, n, n_tiles, tile_px);
+    batch_search_kernel<M, S, 512, MEASURE><<<grid, dim3(512), 0, s>>>(table, first, n, n_tiles, tile_px);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+template <int M, typename S>
+static hipError_t launch_search_ms(int block, dim3 grid, const FrameArgs* table, const uint32_t* first,
+                                   uint32_t n, uint32_t n_tiles, uint32_t tile_px, bool measure, hipStream_t s) {
+  return measure ? launch_search_msm<M, S, true>(block, grid, table, first, n, n_tiles, tile_px, s)
+                 : launch_search_msm<M, S, false>(block, grid, table, first, n, n_tiles, tile_px, s);
+}
+
 template <typename S>
 static hipError_t launch_search_s(int M, int block, dim3 grid, const FrameArgs* table, const uint32_t* first,
-                                  uint32_t n, uint32_t n_tiles, uint32_t tile_px, hipStream_t s) {
+                                  uint32_t n, uint32_t n_tiles, uint32_t tile_px, bool measure, hipStream_t s) {
   switch (M) {
-    case 1: return launch_search_ms<1, S>(block, grid, table, first, n, n_tiles, tile_px, s);
-    case 2: return launch_search_ms<2, S>(block, grid, table, first, n, n_tiles, tile_px, s);
-    case 3: return launch_search_ms<3, S>(block, grid, table, first, n, n_tiles, tile_px, s);
-    case 4: return launch_search_ms<4, S>(block, grid, table, first, n, n_tiles, tile_px, s);
-    case 5: return launch_search_ms<5, S>(block, grid, table, first, n, n_tiles, tile_px, s);
+    case 1: return launch_search_ms<1, S>(block, grid, table, first, n, n_tiles, tile_px, measure, s);
+    case 2: return launch_search_ms<2, S>(block, grid, table, first, n, n_tiles, tile_px, measure, s);
+    case 3: return launch_search_ms<3, S>(block, grid, table, first, n, n_tiles, tile_px, measure, s);
+    case 4: return launch_search_ms<4, S>(block, grid, table, first, n, n_tiles, tile_px, measure, s);
+    case 5: return launch_search_ms<5, S>(block, grid, table, first, n, n_tiles, tile_px, measure, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+// `measure`: some descriptor has a traffic record (see launch_batch).
 static hipError_t launch_search(int M, int dtype, int block, dim3 grid, const FrameArgs* table,
                                 const uint32_t* first, uint32_t n, uint32_t n_tiles, uint32_t tile_px,
-                                hipStream_t s) {
+                                bool measure, hipStream_t s) {
   switch (dtype) {
-    case GMM_F32: return launch_search_s<float>(M, block, grid, table, first, n, n_tiles, tile_px, s);
-    case GMM_F16: return launch_search_s<f16s>(M, block, grid, table, first, n, n_tiles, tile_px, s);
-    case GMM_BF16: return launch_search_s<bf16s>(M, block, grid, table, first, n, n_tiles, tile_px, s);
+    case GMM_F32: return launch_search_s<float>(M, block, grid, table, first, n, n_tiles, tile_px, measure, s);
+    case GMM_F16: return launch_search_s<f16s>(M, block, grid, table, first, n, n_tiles, tile_px, measure, s);
+    case GMM_BF16: return launch_search_s<bf16s>(M, block, grid, table, first, n, n_tiles, tile_px, measure, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -194,6 +202,7 @@ extern "C" gmm_status gmm_batch_apply_static(gmm_handle* const* handles, int32_t
   hipStream_t hs = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   uint32_t next_first = 0;
+  bool measure = false;
   for (int32_t b = 0; b < n && e == hipSuccess; b += kPackPerLaunch) {
     PackArgs p{};
     p.base = static_cast<uint32_t>(b);
@@ -202,6 +211,7 @@ extern "C" gmm_status gmm_batch_apply_static(gmm_handle* const* handles, int32_t
       gmm_handle* h = handles[b + i];
       const gmm_stream_io& s = io[b + i];
       p.a[i] = frame_args(h, s.rgb, s.rgb_pitch_bytes, s.depth, s.depth_pitch_bytes, s.fg_rgb, s.fg_depth, s.fused);
+      measure = measure || p.a[i].wave_bytes != nullptr;
       p.first[i] = next_first;
       next_first += static_cast<uint32_t>((h->npix + t.tile_pixels - 1) / t.tile_pixels);
     }
@@ -213,7 +223,7 @@ extern "C" gmm_status gmm_batch_apply_static(gmm_handle* const* handles, int32_t
   const uint32_t want = static_cast<uint32_t>(t.blocks_per_cu) * static_cast<uint32_t>(cus);
   const dim3 grid(std::max(1u, std::min(want, n_tiles)));
   e = launch_search(handles[0]->cfg.M, handles[0]->cfg.state_dtype, t.block_threads, grid, table, first,
-                    static_cast<uint32_t>(n), n_tiles, static_cast<uint32_t>(t.tile_pixels), hs);
+                    static_cast<uint32_t>(n), n_tiles, static_cast<uint32_t>(t.tile_pixels), measure, hs);
   if (e != hipSuccess) return hip_fail(e, "static batch kernel launch");
   for (int32_t i = 0; i < n; ++i) handles[i]->last_stream = hs;
   return GMM_OK;

@@ -116,6 +116,92 @@ def test_large_single_stream_bit_identical_to_batch():
         batched.close()
 
 
+def _relayout(x, how):
+    """The same pixel values in another layout: 'pitched' rows (wider rows, a view of the first
+    columns), 'offset' (a colour base one byte past an aligned address) or 'dense'."""
+    if x is None or how == "dense":
+        return x
+    h, w = x.shape[0], x.shape[1]
+    if how == "pitched":
+        buf = torch.zeros((h, w + 5) + tuple(x.shape[2:]), dtype=x.dtype, device=DEV)
+        v = buf[:, :w]
+    else:
+        assert x.dtype == torch.uint8
+        buf = torch.zeros(x.numel() + 1, dtype=torch.uint8, device=DEV)
+        v = buf[1:].view(x.shape)
+    v.copy_(x)
+    return v
+
+
+def test_batch_with_pitched_and_offset_frames_bit_identical():
+    """Streams whose frames are not dense (pitched rows, a colour base off 4-byte alignment) take
+    the batched body with the row arithmetic, dense ones the body without it, in one launch; every
+    stream must match the same stream fed dense frames, masks every frame and the whole state."""
+    layouts = [("pitched", "pitched"), ("offset", "dense"), ("dense", "pitched"), ("offset", "dense"),
+               ("dense", "dense")]
+    streams = [Stream(s) for s in SPECS]
+    ref = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
+    segs = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
+    ref_batch, batch = Batch(ref), Batch(segs)
+    try:
+        for t in range(8):
+            frames = _frames(streams, t)
+            ref_batch.apply(frames)
+            batch.apply([(_relayout(r, lr), _relayout(d, ld)) for (r, d), (lr, ld) in zip(frames, layouts)])
+            torch.cuda.synchronize()
+            _compare_bitwise(ref, segs, t)
+        for a, b in zip(ref, segs):
+            assert np.array_equal(a.read_state(), b.read_state())
+    finally:
+        ref_batch.close()
+        batch.close()
+        for s in ref + segs:
+            s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_batch_traffic_record_matches_single_streams(dtype):
+    """With traffic records attached, the batched launch (its counting kernel) adds the same bytes
+    per wave as one launch per stream; after the records are removed, launches add nothing."""
+    streams = [Stream(s) for s in SPECS]
+    single = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, **kwargs(MIX)) for s in SPECS]
+    batched = [Segmenter(s.width, s.height, mods(s), MIX.M, state_dtype=dtype, **kwargs(MIX)) for s in SPECS]
+    rec_s = [torch.zeros((s.npix + 63) // 64, dtype=torch.int64, device=DEV) for s in SPECS]
+    rec_b = [torch.zeros((s.npix + 63) // 64, dtype=torch.int64, device=DEV) for s in SPECS]
+    batch = Batch(batched)
+    try:
+        for t in range(2):   # no records yet
+            frames = _frames(streams, t)
+            for seg, (rgb, dep) in zip(single, frames):
+                _single_step(seg, rgb, dep)
+            batch.apply(frames)
+        for a, b, ra, rb in zip(single, batched, rec_s, rec_b):
+            _abi.gmm_set_traffic_record(a.handle, ra)
+            _abi.gmm_set_traffic_record(b.handle, rb)
+        for t in range(2, 7):
+            frames = _frames(streams, t)
+            for seg, (rgb, dep) in zip(single, frames):
+                _single_step(seg, rgb, dep)
+            batch.apply(frames)
+        torch.cuda.synchronize()
+        for i, (ra, rb) in enumerate(zip(rec_s, rec_b)):
+            assert int(ra.sum()) > 0, i
+            assert torch.equal(ra, rb), i
+        for b in batched:
+            _abi.gmm_set_traffic_record(b.handle, None)
+        kept = [r.clone() for r in rec_b]
+        batch.apply(_frames(streams, 7))
+        torch.cuda.synchronize()
+        for r, k in zip(rec_b, kept):
+            assert torch.equal(r, k)
+    finally:
+        for a in single:
+            _abi.gmm_set_traffic_record(a.handle, None)
+        batch.close()
+        for s in single + batched:
+            s.close()
+
+
 def test_autotune_leaves_state_untouched_and_picks_a_candidate():
     streams = [Stream(s) for s in SPECS]
     segs = [Segmenter(s.width, s.height, mods(s), MIX.M, **kwargs(MIX)) for s in SPECS]
