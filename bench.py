@@ -499,7 +499,7 @@ def bench_batch(args) -> int:
                    "launch": "graph", "tuning": list(batch.tuning()), "autotune_ms": tune_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"rgbd::batch_kernel<{M}, {dtype}, {batch.tuning()[0]}>",
+                     "kernel": f"rgbd::batch_kernel<{M}, {dtype}, {batch.tuning()[0]}, false>",
                      "algorithmic_bytes_per_launch": alg, "full_rewrite_bytes_per_launch": full,
                      "full_rewrite_frac": full / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_us": ms_step * 1e3,
