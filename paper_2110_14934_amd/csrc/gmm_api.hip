@@ -137,7 +137,9 @@ static gmm_status validate_config(const gmm_config* c) {
   return GMM_OK;
 }
 
-// Constants of one mixture over C channels; `mod` picks sigma0 / var_min (0 colour, 1 depth).
+// Constants of one mixture over C channels; `mod` picks sigma0 / var_min (0 colour, 1 depth). Only
+// var0, var_min, hole_skip and rho_scale depend on the modality: the kernels read every other field
+// of a handle's depth constants from its colour constants (depth_consts).
 static ModelConsts make_consts(const gmm_config& c, int mod, int C, bool hole_skip) {
   ModelConsts k{};
   k.alpha = c.alpha;

@@ -31,7 +31,7 @@ struct FrameArgs {
   uint64_t* fg_depth;
   uint64_t* fused;
   ModelConsts kc;          // colour constants
-  ModelConsts kd;          // depth constants
+  ModelConsts kd;          // depth constants (the fields both modalities share equal kc's: depth_consts)
   int32_t mode;            // kModeRGB | kModeDepth | kModeFuse bits of this stream
   int32_t pad_;
   uint64_t* wave_bytes;    // optional: per-wave running total of state bytes moved (measurement)
